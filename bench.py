@@ -1,0 +1,176 @@
+"""Time-to-steady-state benchmark of the quantum-PageRank solver on one MI355X.
+
+Workload (one "step" = one pass of the whole path over the batch): the
+scale-free directed graph N=922 (Barabasi-Albert m=3, random edge direction,
+10 % reciprocal, seed 0), Google damping 0.85, built on the GPU, then solved
+to ||L(rho)||_F < 1e-8 from rho0 = I/N with RK4 dt = 0.01 in FP64 at each of
+omega = 0.2, 0.5, 0.8, and ranked.  `value` is the mean time-to-steady-state
+per solve in seconds (inputs resident in HBM; host readback of the device
+flag once per chunk is part of it).
+
+Also reported (same graph, same omegas): the mixed-precision solves (BF16x3
+and FP32 products with FP64 judge), the roofline of the dominant kernel (the
+FP64 commutator product, timed with HIP events on the solve's stream), and
+the CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-steady-state N=922/4096: FP64 plain vs mixed+warm-start; solves/s"
+OMEGAS = (0.2, 0.5, 0.8)
+N, M_BA, DT, TOL = 922, 3, 0.01, 1e-8
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def solve_all(Q, P, prec, rho0_fn=None):
+    out = []
+    for w in OMEGAS:
+        r = Q.steady_state(P, w, DT, TOL, 400000, prec=prec,
+                           rho0=None if rho0_fn is None else rho0_fn(w))
+        out.append(r)
+    return out
+
+
+def cpu_baseline(g, gpu_steps):
+    """Oracle RK4 steps on the host, extrapolated to the GPU's step counts."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    R = O.problem_ref(g.n, g.src, g.dst)
+    rho = np.eye(g.n, dtype=np.complex128) / g.n
+    sample_steps = 30
+    t0 = time.perf_counter()
+    for w in OMEGAS:
+        O.rk4_ref(rho, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, w), DT, sample_steps // 3)
+    dt = time.perf_counter() - t0
+    per_step = dt / sample_steps
+    per_solve = per_step * float(np.mean(gpu_steps))
+    return {
+        "value": per_solve, "unit": "s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"{sample_steps} RK4 steps of the numpy/scipy FP64 oracle at N={g.n} "
+                   f"(10 per omega in {list(OMEGAS)}), {per_step * 1e3:.1f} ms/step, "
+                   f"extrapolated to the GPU's mean step count {float(np.mean(gpu_steps)):.0f}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
+              "has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2003_04930_amd import inputs, qpr as Q
+
+    torch.cuda.set_device(0)
+    g = inputs.ba_digraph(N, M_BA, seed=0)
+    log(f"graph {g}")
+    t_build0 = time.perf_counter()
+    P = Q.Problem.from_graph(g)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_build0
+
+    for k in range(args.warmup):
+        log(f"warmup {k}")
+        solve_all(Q, P, "fp64")
+    torch.cuda.synchronize()
+    log("timed region")
+    t0 = time.perf_counter()
+    results = None
+    for k in range(args.steps):
+        results = solve_all(Q, P, "fp64")
+        log(f"step {k} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    steps = [r.stats["steps"] for r in results]
+    per_omega = {str(w): {"seconds": r.stats["seconds"], "rk4_steps": r.stats["steps"],
+                          "residual": r.stats["residual"]} for w, r in zip(OMEGAS, results)}
+    value = ms_per_step / 1e3 / len(OMEGAS)
+    log(f"fp64: {value:.3f} s/solve, steps {steps}")
+
+    # dominant kernel: the FP64 commutator product, timed on the same stream
+    rho_ss = results[-1].rho
+    gemm_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
+    ld = P.ld
+    flops = 4.0 * N ** 3                       # algorithmic: two real N x N x N products
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    epi_bytes = 16.0 * N * N * 9               # stage-1 pass: 5 complex reads + 4 writes
+    epi_gbs = epi_bytes / (epi_ms * 1e-3) / 1e9
+    log(f"product {gemm_ms * 1e3:.1f} us ({achieved:.1f} TF/s), epilogue {epi_ms * 1e3:.1f} us "
+        f"({epi_gbs:.0f} GB/s)")
+
+    extra = {"per_omega_fp64": per_omega, "build_seconds": t_build,
+             "solves_per_s_fp64": 1.0 / value,
+             "epilogue": {"achieved_GBs": epi_gbs, "peak_GBs": HBM_PEAK_GBS,
+                          "frac": epi_gbs / HBM_PEAK_GBS, "us": epi_ms * 1e3,
+                          "bytes_per_launch": epi_bytes},
+             "product_us": gemm_ms * 1e3, "ld": ld}
+
+    if not args.no_mixed:
+        for prec in ("bf16x3", "fp32"):
+            t0m = time.perf_counter()
+            rm = solve_all(Q, P, prec)
+            torch.cuda.synchronize()
+            tm = (time.perf_counter() - t0m) / len(OMEGAS)
+            err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rm, results))
+            pm, _ = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec=prec, reps=100)
+            extra[f"mixed_{prec}"] = {
+                "seconds_per_solve": tm, "rk4_steps": [r.stats["steps"] for r in rm],
+                "folds": [r.stats["folds"] for r in rm],
+                "max_abs_drho_vs_fp64": err, "product_us": pm * 1e3,
+                "speedup_vs_fp64": value / tm}
+            log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(g, steps)
+        log(f"cpu oracle ~{cpu['value']:.1f} s/solve")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"ba{N}-m{M_BA}-s0 FP64 steady state, omega in {list(OMEGAS)}, "
+                               f"dt={DT}, tol={TOL}, rho0=I/N; value = seconds per solve",
+                   "n": N, "omegas": list(OMEGAS), "tol": TOL, "dt": DT},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

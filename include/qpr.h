@@ -1,0 +1,301 @@
+/*
+ * qpr.h -- C ABI of libqpr, an MI355X (gfx950) solver for the steady state of
+ * quantum PageRank (Tang, He, Shi, Zhu, Lee, Wang, Jin, "TensorFlow Solver for
+ * Quantum PageRank in Large-Scale Networks", arXiv:2003.04930).
+ *
+ * The solver integrates the quantum-stochastic-walk Lindblad equation (Eq. (1),
+ * Supplementary Eq. (S7))
+ *
+ *   d rho/dt = L(rho) = -i (1-omega) [H, rho] + omega D_G(rho),
+ *   D_G(rho) = sum_ij ( L_ij rho L_ij^dag - 1/2 {L_ij^dag L_ij, rho} ),
+ *   L_ij     = sqrt(G_ij) |i><j|,
+ *
+ * with the classical four-stage Runge-Kutta method (Supplementary Note 2)
+ * until ||L(rho)||_F < tol.  The N^2 x N^2 Liouvillian of Eq. (2) is never
+ * formed: the commutator is a real matrix product X = H_off [Re rho | Im rho]
+ * on the matrix cores and [H, rho] = X - X^dag + [diag(h), rho]; the jump sum
+ * collapses to diag(G p) - 1/2 (d_a + d_b) rho_ab with p = diag(rho) and
+ * d_j = sum_i G_ij.
+ *
+ * Conventions (every entry point):
+ *  - Status codes: QPR_OK (0) or a negative qpr_status; no C++ exception
+ *    crosses the ABI; qpr_last_error() returns this thread's message for the
+ *    last non-OK status.
+ *  - Memory: the library never allocates or frees device memory.  The caller
+ *    owns a problem arena (qpr_problem_bytes) and a workspace
+ *    (qpr_workspace_bytes); both are device memory, 256-byte aligned.
+ *  - Density matrices cross the ABI as planar FP64 device arrays of 2*n*n
+ *    doubles: rho[a*n+b] = Re rho_ab, rho[n*n + a*n+b] = Im rho_ab (row-major,
+ *    rho_ab = <a|rho|b>).  They must be Hermitian.
+ *  - Streams: every call enqueues on `stream` (NULL = the null stream).
+ *    qpr_rhs and qpr_rk4_step are asynchronous; qpr_build_google,
+ *    qpr_steady_state and qpr_batch_solve synchronise the stream.
+ *  - Concurrency: calls that share a workspace must not overlap.
+ */
+#ifndef QPR_H
+#define QPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* qpr_stream_t; /* the same type as hipStream_t */
+
+typedef enum {
+  QPR_OK = 0,
+  QPR_E_ARG = -1,           /* invalid argument (message says which)          */
+  QPR_E_HIP = -2,           /* a HIP runtime call failed                      */
+  QPR_E_NOT_CONVERGED = -3, /* max_steps reached; rho holds the last state    */
+  QPR_E_NONFINITE = -4,     /* NaN or Inf met in the state or right-hand side */
+  QPR_E_UNSTABLE = -5,      /* dt outside the RK4 stability bound             */
+  QPR_E_WORKSPACE = -6      /* arena or workspace too small                   */
+} qpr_status;
+
+/* Long-distance hopping ("teleport") matrix T of the Google matrix. */
+typedef enum {
+  QPR_TELEPORT_PAPER_F = 0, /* Eq. (S2): 1/(N-1) off the diagonal, 0 on it */
+  QPR_TELEPORT_UNIFORM = 1  /* 1/N everywhere                               */
+} qpr_teleport;
+
+/* Hamiltonian of the coherent part. */
+typedef enum {
+  QPR_HDIAG_ZERO = 0, /* symmetrised adjacency max(A, A^T), zero diagonal     */
+  QPR_HDIAG_PAPER = 1 /* Eq. (S6): -max(A_ij, A_ji), diagonal -outDeg(j)      */
+} qpr_hdiag;
+
+/* Arithmetic of the commutator product (the epilogue is always FP64). */
+typedef enum {
+  QPR_FP64 = 0,  /* FP64 matrix cores                                        */
+  QPR_FP32 = 1,  /* FP32 matrix cores                                        */
+  QPR_BF16X3 = 2 /* rho split in three bf16 slices, FP32 accumulation        */
+} qpr_prec;
+
+/*
+ * A built problem.  Filled by qpr_build_google; the device pointers point into
+ * the caller's arena, which must outlive every use of the struct.
+ */
+typedef struct {
+  int32_t n;            /* nodes                                              */
+  int32_t ld;           /* leading dimension of internal planes (n rounded up to 64) */
+  int64_t n_edges_in;   /* edges passed in                                    */
+  int64_t nnz_a;        /* distinct directed edges after dropping loops/duplicates */
+  int64_t nnz_h;        /* nonzeros of the off-diagonal Hamiltonian           */
+  int32_t n_self_loops; /* self-loops dropped                                 */
+  int32_t n_dangling;   /* nodes without out-links                            */
+  double alpha;         /* damping of the Google matrix                       */
+  int32_t teleport;     /* qpr_teleport                                       */
+  int32_t hdiag;        /* qpr_hdiag                                          */
+  double h_lo, h_hi;    /* Gershgorin interval containing the spectrum of H   */
+  int32_t pagerank_iters; /* power iterations used for `pagerank`             */
+  int32_t reserved;
+  /* device arrays inside the arena */
+  double* h_off;        /* ld*ld, off-diagonal H (0 or +-1), zero padded      */
+  float* h_off_f32;     /* ld*ld, the same values in FP32                     */
+  uint16_t* h_off_bf16; /* ld*ld, the same values in bf16                     */
+  double* h_diag;       /* n, diagonal of H                                   */
+  double* d;            /* n, column sums of G                                */
+  double* inv_outdeg;   /* n, 1/outDeg(j), 0 for a dangling node              */
+  int32_t* dangling;    /* n, 1 if node j has no out-links                    */
+  int32_t* outdeg;      /* n                                                  */
+  int32_t* indeg;       /* n                                                  */
+  int32_t* in_ptr;      /* n+1, CSR of in-links: row a lists j with j -> a     */
+  int32_t* in_idx;      /* nnz_a, ascending within a row                      */
+  int32_t* out_ptr;     /* n+1, CSR of out-links: row j lists a with j -> a    */
+  int32_t* out_idx;     /* nnz_a                                              */
+  double* pagerank;     /* n, stationary vector of G (power iteration)        */
+  void* arena;
+  size_t arena_bytes;
+} qpr_problem;
+
+/* Per-solve statistics (host struct). */
+typedef struct {
+  int64_t steps;          /* RK4 steps taken (the state returned is y_steps)  */
+  int64_t rhs_evals;      /* right-hand-side evaluations, all precisions      */
+  int64_t rhs_evals_fp64; /* of which with the FP64 product                   */
+  int64_t folds;          /* defect-correction folds (mixed precision)        */
+  double t;               /* integrated time                                  */
+  double residual;        /* ||L(rho)||_F of the returned state, FP64         */
+  double trace_err;       /* |tr rho - 1| of the returned state               */
+  double herm_err;        /* max |rho - rho^dag| of the returned state        */
+  double min_diag;        /* min_a Re rho_aa                                  */
+  double seconds;         /* host wall time of the call                       */
+  int32_t converged;      /* 1 if residual < tol                              */
+  int32_t status;         /* qpr_status of the call                           */
+} qpr_stats;
+
+/* Solver options; pass NULL for the defaults in brackets. */
+typedef struct {
+  int32_t chunk;      /* RK4 steps per host check of the device flag [64]     */
+  int32_t use_graph;  /* replay each chunk as a captured HIP graph [1]        */
+  int32_t fold_every; /* mixed precision: steps between FP64 folds [=chunk]   */
+  int32_t renorm;     /* mixed precision: divide by the trace at folds [1]    */
+  int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1]  */
+  int32_t reserved[3];
+} qpr_opts;
+
+/* ------------------------------------------------------------------ build */
+
+/* Bytes of the problem arena for n nodes and n_edges input edges. */
+size_t qpr_problem_bytes(int32_t n, int64_t n_edges);
+
+/*
+ * Build the Google matrix G = alpha S + (1-alpha) T (Eq. (S4) read as the
+ * column-stochastic Google matrix; S is the out-degree-normalised adjacency of
+ * Supplementary Note 1, a dangling column takes the teleport column), the
+ * Hamiltonian of Eq. (S6) per `hdiag`, the column sums d of G and the PageRank
+ * vector of G by power iteration.
+ *   n        number of nodes, n >= 2
+ *   src,dst  HOST arrays of n_edges int32: edge src[e] -> dst[e], meaning
+ *            A[dst][src] = 1 (Supplementary Note 1).  0 <= src,dst < n.
+ *            Duplicates collapse; self-loops are dropped and counted.
+ *   alpha    in [0, 1]
+ *   arena    device memory of at least qpr_problem_bytes(n, n_edges)
+ *   out      host struct filled on QPR_OK
+ * Errors: QPR_E_ARG (n < 2, bad alpha/teleport/hdiag, edge out of range, NULL
+ * pointer), QPR_E_WORKSPACE (arena too small), QPR_E_HIP.  Synchronises.
+ */
+qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t* src,
+                            const int32_t* dst, double alpha, int32_t teleport,
+                            int32_t hdiag, void* arena, size_t arena_bytes,
+                            qpr_problem* out, qpr_stream_t stream);
+
+/* Bytes of workspace a solve of an n-node problem needs at precision prec. */
+size_t qpr_workspace_bytes(int32_t n, int32_t prec);
+
+/* ------------------------------------------------------------------ solve */
+
+/*
+ * out = L(rho), the right-hand side of Eq. (1) (reading above), with the
+ * commutator product at precision `prec` and everything else in FP64.
+ *   rho, out  device, 2*n*n planar FP64 (may not alias)
+ * Errors: QPR_E_ARG (omega outside [0,1], NULL), QPR_E_WORKSPACE, QPR_E_HIP.
+ * Asynchronous.
+ */
+qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho,
+                   double* out, int32_t prec, void* ws, size_t ws_bytes,
+                   qpr_stream_t stream);
+
+/*
+ * nsteps classical RK4 steps of size dt (Supplementary Note 2) applied to rho
+ * in place.  If diag_out (device, 4 doubles) is not NULL it receives
+ * [ ||L(y)||_F^2 at the start of the last step, tr y_final, max|y - y^dag|,
+ * nonfinite flag ] of the final state.
+ * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP.
+ * Asynchronous.
+ */
+qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt,
+                        int32_t nsteps, double* rho, int32_t prec,
+                        double* diag_out, void* ws, size_t ws_bytes,
+                        qpr_stream_t stream);
+
+/*
+ * Integrate from rho (in: rho0) until the first step n with
+ * ||L(y_n)||_F < tol, FP64-judged, and return y_n in rho.  With prec != FP64
+ * the solve is a defect correction: an FP64 anchor rho_a with FP64 residual
+ * r_a = L(rho_a), and d delta/dt = r_a + L_prec(delta) integrated with the
+ * low-precision product, folded into the anchor (and trace-renormalised) every
+ * opts->fold_every steps; convergence is judged on the FP64 residual.
+ *   rank   device int32[n] or NULL: nodes by descending Re rho_aa, ties by
+ *          ascending index (computed in FP64)
+ *   stats  host, may be NULL
+ *   opts   may be NULL
+ * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP,
+ * QPR_E_NONFINITE, QPR_E_NOT_CONVERGED (rho then holds the last state so the
+ * call can be resumed).  Synchronises once per chunk.
+ */
+qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
+                            double tol, int64_t max_steps, int32_t prec,
+                            double* rho, int32_t* rank, qpr_stats* stats,
+                            const qpr_opts* opts, void* ws, size_t ws_bytes,
+                            qpr_stream_t stream);
+
+/*
+ * Rank nodes by descending p (device, n doubles), ties by ascending index,
+ * into order (device int32[n]).  Asynchronous.
+ */
+qpr_status qpr_rank(int32_t n, const double* p, int32_t* order,
+                    qpr_stream_t stream);
+
+/* ------------------------------------------------------- learned warm start */
+/*
+ * A small message-passing network predicts diag(rho_ss) so the integrator
+ * can start from rho0 = diag(p_hat) (the FP64 solve still finishes and judges;
+ * the paper has no learned part).  Per node i:
+ *   x_i  = [log(1+in_i), log(1+out_i), N * PageRank_i, omega]
+ *   h'_i = ReLU(Ws h_i + Win mean_{j->i} h_j + Wout mean_{i->j} h_j + b)  (3 layers, width 64)
+ *   s_i  = w . h_i + c,  p_hat = softmax(s) within each graph
+ *   loss = mean over graphs of KL(p || p_hat)
+ * Parameters are one FP32 array of qpr_mpnn_param_count() values:
+ * for l = 0,1,2: Ws_l, Win_l, Wout_l (each 64 x F_l row-major, F_0 = 4,
+ * F_1 = F_2 = 64), b_l (64); then w (64) and c (1).
+ * A batch is block-diagonal: graphs are concatenated and node ids are global.
+ */
+typedef struct {
+  int32_t n_nodes;         /* total nodes                                    */
+  int32_t n_graphs;        /* graphs                                         */
+  const float* x;          /* n_nodes x 4 features (qpr_mpnn_features)       */
+  const int32_t* in_ptr;   /* n_nodes+1; row i lists j with j -> i           */
+  const int32_t* in_idx;
+  const int32_t* out_ptr;  /* n_nodes+1; row i lists j with i -> j           */
+  const int32_t* out_idx;
+  const float* inv_in;     /* 1/in-degree (0 if none)                        */
+  const float* inv_out;    /* 1/out-degree (0 if none)                       */
+  const int32_t* graph_ptr;/* n_graphs+1 node offsets                         */
+} qpr_mpnn_batch;          /* every pointer is device memory                  */
+
+int32_t qpr_mpnn_param_count(void);
+/* workspace (device) for one forward + backward over a batch of this size */
+size_t qpr_mpnn_workspace_bytes(int32_t n_nodes, int32_t n_graphs);
+/* features x (n x 4), inv_in, inv_out (n) of one built problem, on device */
+qpr_status qpr_mpnn_features(const qpr_problem* P, double omega, float* x,
+                             float* inv_in, float* inv_out, qpr_stream_t stream);
+/* forward pass; p_hat (device, n_nodes) may be NULL; keeps activations in ws */
+qpr_status qpr_mpnn_forward(const qpr_mpnn_batch* batch, const float* params,
+                            float* p_hat, void* ws, size_t ws_bytes,
+                            qpr_stream_t stream);
+/* backward pass after qpr_mpnn_forward on the same ws: grads (device,
+   param_count) = d loss / d params; loss (device, 1 float) may be NULL.
+   Deterministic: fixed-order reductions, no floating-point atomics. */
+qpr_status qpr_mpnn_backward(const qpr_mpnn_batch* batch, const float* params,
+                             const float* p_true, float* grads, float* loss,
+                             void* ws, size_t ws_bytes, qpr_stream_t stream);
+/* one Adam step (Kingma & Ba), step counted from 1, on device arrays */
+qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
+                         int32_t count, int32_t step, float lr, float b1,
+                         float b2, float eps, qpr_stream_t stream);
+
+/* ---------------------------------------------------------- measurement */
+
+/*
+ * Time the two kernels of one right-hand-side stage on `stream` with HIP
+ * events: `reps` back-to-back launches of the commutator product
+ * X = H_off [Re rho | Im rho] (the real products of the coherent term of
+ * Eq. (1)) at precision `prec` with tile configuration `cfg` (-1 = default),
+ * then `reps` launches of the fused stage-1 epilogue.
+ *   rho     device, 2*n*n planar FP64 operand (unchanged)
+ *   ms_out  HOST double[2]: mean milliseconds per product launch and per
+ *           epilogue launch
+ * Errors: QPR_E_ARG, QPR_E_WORKSPACE, QPR_E_HIP.  Synchronises.
+ */
+qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32_t prec,
+                            int32_t cfg, int32_t reps, const double* rho,
+                            double* ms_out, void* ws, size_t ws_bytes,
+                            qpr_stream_t stream);
+
+/* Number of product tile configurations at precision prec, and their names. */
+int32_t qpr_product_configs(int32_t prec);
+const char* qpr_product_config_name(int32_t prec, int32_t cfg);
+
+/* Message for this thread's last non-OK status ("" if none). */
+const char* qpr_last_error(void);
+
+/* Library version string. */
+const char* qpr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPR_H */

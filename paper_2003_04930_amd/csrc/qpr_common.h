@@ -1,0 +1,145 @@
+// Internal declarations shared by the libqpr sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/qpr.h"
+
+namespace qpr {
+
+constexpr int kPad = 64;          // internal planes are padded to a multiple of this
+constexpr size_t kAlign = 256;    // every carved region starts on this boundary
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+inline int pad_n(int n) { return (n + kPad - 1) / kPad * kPad; }
+
+// Error reporting: sets this thread's last message and returns the status.
+qpr_status fail(qpr_status s, const char* fmt, ...);
+void clear_error();
+
+#define QPR_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::qpr::fail(QPR_E_HIP, "%s failed: %s (%s:%d)", #call,            \
+                         hipGetErrorString(e_), __FILE__, __LINE__);           \
+  } while (0)
+
+// Device-resident control block of one solve.  Written only by the last
+// workgroup of a reducing launch (one lane, vector stores) and read by every
+// later launch on the stream.
+struct DevState {
+  double resid2;        // ||L(y_n)||_F^2 measured by the latest stage-1 pass
+  double tol2;          // tol^2
+  long long step;       // RK4 steps whose stage 1 has been started
+  long long max_steps;  // stop (not converged) once step reaches this
+  long long conv_step;  // step index whose state met the tolerance
+  long long rhs_evals;  // product launches that ran (counted by stage-1 and RHS passes)
+  int stop;             // non-zero: every solver launch returns at once
+  int converged;
+  int nonfinite;
+  int check;            // 1: stage 1 tests the tolerance
+  unsigned int ticket;  // last-workgroup counter, reset by the last workgroup
+  int hold;             // non-zero: low-precision step launches return at once
+  double judge2;        // mixed precision: latest FP64 ||L(rho_a)||_F^2
+  long long folds;      // mixed precision: FP64 judge evaluations
+  double aux[8];        // final-state diagnostics (trace, herm, min diag, ...)
+};
+
+// Values of EpiArgs::check
+enum CheckMode {
+  CHK_NONE = 0,   // record ||k||^2 only
+  CHK_PLAIN = 1,  // stage 1 of the FP64 solve: converge / count steps
+  CHK_DELTA = 2,  // stage 1 of a low-precision delta step: hold when the estimate meets tol
+  CHK_JUDGE = 3   // FP64 residual of the anchor: converge, or release the hold
+};
+
+// Workspace carved from the caller's buffer.  Planes are ld*ld.
+struct Ws {
+  int n = 0, ld = 0, prec = 0;
+  double *yn_r = nullptr, *yn_i = nullptr;   // y_n (or the anchor delta in mixed mode)
+  double *y1_r = nullptr, *y1_i = nullptr;   // stage states (ping)
+  double *y2_r = nullptr, *y2_i = nullptr;   // stage states (pong)
+  double *acc_r = nullptr, *acc_i = nullptr; // RK4 accumulator
+  double *x_r = nullptr, *x_i = nullptr;     // X = H_off * Y (FP64 products)
+  double *ra_r = nullptr, *ra_i = nullptr;   // mixed: FP64 anchor residual L(rho_a)
+  double *an_r = nullptr, *an_i = nullptr;   // mixed: FP64 anchor rho_a
+  float *xf_r = nullptr, *xf_i = nullptr;    // FP32 products (mixed modes)
+  float *lo_r = nullptr, *lo_i = nullptr;    // FP32 operand copy (QPR_FP32)
+  uint16_t* sl = nullptr;                    // bf16 slices: [plane][slice][ld*ld]
+  double *p_n = nullptr, *p_1 = nullptr, *p_2 = nullptr, *p_a = nullptr; // diagonals (n)
+  double* partials = nullptr;                // per-workgroup partial sums
+  int max_partials = 0;
+  DevState* st = nullptr;
+  double* scal = nullptr;                    // small scratch (16 doubles)
+};
+
+size_t ws_bytes(int n, int prec);
+bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* out);
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+
+// Problem view handed to the epilogue.
+struct ProbView {
+  int n, ld, teleport;
+  double alpha;
+  const double *h, *d, *inv_outdeg;
+  const int *dangling, *in_ptr, *in_idx;
+};
+ProbView view_of(const qpr_problem* P);
+
+enum EpiMode { EPI_RHS = 0, EPI_S1 = 1, EPI_S2 = 2, EPI_S3 = 3, EPI_S4 = 4 };
+
+// Which buffer kind the epilogue reads X from and what lowp copy it writes.
+enum OpKind { OP_F64 = 0, OP_F32 = 1, OP_BF16X3 = 2 };
+
+struct EpiArgs {
+  const double *xr, *xi;      // FP64 X (OP_F64)
+  const float *xfr, *xfi;     // FP32 X (OP_F32 / OP_BF16X3)
+  const double *ysr, *ysi;    // stage input Y_s
+  const double* ps;           // diag of Y_s
+  const double *ynr, *yni;    // y_n
+  double *accr, *acci;        // accumulator
+  double *outr, *outi;        // stage output (y_{s+1}, y_n at stage 4, or L(Y) for RHS)
+  double* pout;               // diag of the output state
+  const double *rar, *rai;    // mixed mode: FP64 anchor residual added to L (or null)
+  float *lor, *loi;           // FP32 copy of the output state (or null)
+  uint16_t* slices;           // bf16 slices of the output state (or null)
+  double omega, cdt;          // cdt: c_s * dt for stages 1..3, dt/6 for stage 4
+  int mode, xkind;
+  int check;                  // CheckMode
+  int gate;                   // 1: also return when DevState::hold is set
+};
+
+hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w,
+                       const double* yr, const double* yi, int gate, hipStream_t s);
+hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w,
+                           hipStream_t s);
+hipError_t launch_pad_in(const double* rho, int n, int ld, double* r, double* i,
+                         double* p, hipStream_t s);
+hipError_t launch_pad_out(const double* r, const double* i, int n, int ld,
+                          double* rho, hipStream_t s);
+hipError_t launch_to_lowp(int kind, const double* r, const double* i, int n,
+                          int ld, const Ws& w, hipStream_t s);
+hipError_t launch_state_init(DevState* st, double tol, long long max_steps,
+                             int check, hipStream_t s);
+hipError_t launch_state_stats(const double* r, const double* i, const double* p,
+                              int n, int ld, const Ws& w, hipStream_t s);
+hipError_t launch_rank(int n, const double* p, int* order, hipStream_t s);
+hipError_t launch_axpy_planes(double* yr, double* yi, const double* xr,
+                              const double* xi, double a, int n, int ld,
+                              double* p, const DevState* st, hipStream_t s);
+hipError_t launch_trace(const double* p, int n, DevState* st, hipStream_t s);
+hipError_t launch_fill(void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_scale_planes(double* r, double* i, double* p, int n, int ld,
+                               const DevState* st, hipStream_t s);
+
+int gemm_num_cfgs(int kind);
+const char* gemm_cfg_name(int kind, int cfg);
+int gemm_default_cfg(int kind, int n);
+
+}  // namespace qpr

@@ -1,0 +1,370 @@
+// Commutator product X = H_off * Y on the CDNA4 matrix cores.
+//
+// The coherent part of Eq. (1) needs [H, rho].  With H real symmetric and rho
+// Hermitian, rho H = (H rho)^dag, so one complex product X = H_off rho (two
+// real products, one per plane of rho) gives [H_off, rho] = X - X^dag; the
+// epilogue applies that and the diagonal of H.  H_off is symmetric, so the
+// MFMA A-fragment A[i][k] = H[m0+i][k0+k] equals H[k0+k][m0+i] and is read
+// along rows of H, the same way as the B-fragment is read from Y.
+//
+// FP64: v_mfma_f64_16x16x4f64.  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register r of lane l holds D[4r + l/16][l%16].
+// Tiles are staged through LDS with double buffering (global loads of tile
+// k+1 are in flight while tile k is multiplied).
+#include <cstdio>
+
+#include "qpr_common.h"
+#include "qpr_device.h"
+
+namespace qpr {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Bijective map from the hardware workgroup id (dispatched round-robin over
+// the 8 XCDs) to a logical tile id such that each XCD receives a contiguous
+// range of logical tiles, which then share operand blocks in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// ------------------------------------------------------------ FP64 / FP32
+// One template for both: 16x16x4 MFMA, one operand value per lane.
+//   f64: accumulator register r of lane l holds D[4r + l/16][l%16]
+//   f32: accumulator register r of lane l holds D[4(l/16) + r][l%16]
+template <typename T>
+struct MfmaK4;
+template <>
+struct MfmaK4<double> {
+  typedef d4 acc_t;
+  typedef double2 vec_t;
+  static constexpr int EV = 2;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int r, int lr) { return 4 * r + lr; }
+};
+template <>
+struct MfmaK4<float> {
+  typedef f4 acc_t;
+  typedef float4 vec_t;
+  static constexpr int EV = 4;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int r, int lr) { return 4 * lr + r; }
+};
+
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_k4(const T* __restrict__ H, const T* __restrict__ Yr, const T* __restrict__ Yi,
+              T* __restrict__ Xr, T* __restrict__ Xi, int ld, const DevState* __restrict__ st,
+              int gate) {
+  typedef MfmaK4<T> M;
+  typedef typename M::acc_t acc_t;
+  typedef typename M::vec_t vec_t;
+  constexpr int EV = M::EV;
+  constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
+  constexpr int BK = 16;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int AP = BM + EV, BP = BN + EV;
+  constexpr int NA = BK * BM / EV / NT, NB = BK * BN / EV / NT;
+  static_assert(NA * NT * EV == BK * BM && NB * NT * EV == BK * BN, "tile/thread mismatch");
+  __shared__ T As[2][BK * AP];
+  __shared__ T Bs[2][2][BK * BP];
+  if (st->stop || (gate && st->hold)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (logical % tiles_m) * BM, n0 = (logical / tiles_m) * BN;
+  const int wm0 = (wave % NWM) * WM, wn0 = (wave / NWM) * WN;
+
+  acc_t acc[2][FM][FN];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[p][i][j][r] = (T)0;
+
+  vec_t ra[NA], rb[2][NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT, row = v / (BM / EV), c = v % (BM / EV);
+      ra[u] = *reinterpret_cast<const vec_t*>(H + (size_t)(k0 + row) * ld + m0 + EV * c);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT, row = v / (BN / EV), c = v % (BN / EV);
+      const size_t o = (size_t)(k0 + row) * ld + n0 + EV * c;
+      rb[0][u] = *reinterpret_cast<const vec_t*>(Yr + o);
+      rb[1][u] = *reinterpret_cast<const vec_t*>(Yi + o);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT, row = v / (BM / EV), c = v % (BM / EV);
+      *reinterpret_cast<vec_t*>(&As[buf][row * AP + EV * c]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT, row = v / (BN / EV), c = v % (BN / EV);
+      *reinterpret_cast<vec_t*>(&Bs[buf][0][row * BP + EV * c]) = rb[0][u];
+      *reinterpret_cast<vec_t*>(&Bs[buf][1][row * BP + EV * c]) = rb[1][u];
+    }
+  };
+
+  const int KT = ld / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T a[FM], b[2][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = As[buf][(kk + lr) * AP + wm0 + i * 16 + lc];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        b[0][j] = Bs[buf][0][(kk + lr) * BP + wn0 + j * 16 + lc];
+        b[1][j] = Bs[buf][1][(kk + lr) * BP + wn0 + j * 16 + lc];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[p][i][j] = M::mma(a[i], b[p][j], acc[p][i][j]);
+    }
+    if (kt + 1 < KT) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    T* X = p ? Xi : Xr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm0 + i * 16 + M::out_row(r, lr);
+          const int col = n0 + wn0 + j * 16 + lc;
+          X[(size_t)row * ld + col] = acc[p][i][j][r];
+        }
+  }
+}
+
+// ---------------------------------------------------------------- BF16x3
+// X_p = H * (s1 + s2 + s3) with FP32 accumulation on v_mfma_f32_16x16x32_bf16.
+// Lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16], so
+// both operands are needed contiguous along k.  H is symmetric, so row m of H
+// is its column m; the slices of R are stored row-major (R is symmetric) and
+// the slices of the imaginary plane hold -I (I is antisymmetric), so row j of
+// every stored slice is column j of the matrix it represents.
+// Slice layout: sl[(p*3 + s) * ld*ld + row*ld + k], p = 0 real, 1 imaginary.
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_bf16x3(const uint16_t* __restrict__ H, const uint16_t* __restrict__ sl,
+                  float* __restrict__ Xr, float* __restrict__ Xi, int ld,
+                  const DevState* __restrict__ st, int gate) {
+  constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
+  constexpr int BK = 32;          // one MFMA depth
+  constexpr int RS = BK + 8;      // padded LDS row (bf16 elements): 80 bytes
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int NA = BM * (BK / 8) / NT;      // uint4 loads per thread, A
+  constexpr int NB = BN * (BK / 8) / NT;      // per plane-slice, B
+  static_assert(NA * NT == BM * BK / 8 && NB * NT == BN * BK / 8, "tile/thread mismatch");
+  __shared__ uint16_t As[2][BM * RS];
+  __shared__ uint16_t Bs[2][6][BN * RS];
+  if (st->stop || (gate && st->hold)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (logical % tiles_m) * BM, n0 = (logical / tiles_m) * BN;
+  const int wm0 = (wave % NWM) * WM, wn0 = (wave / NWM) * WN;
+  const size_t plane = (size_t)ld * ld;
+
+  f4 acc[2][FM][FN];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[p][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  uint4 ra[NA], rb[6][NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
+      ra[u] = *reinterpret_cast<const uint4*>(H + (size_t)(m0 + row) * ld + k0 + 8 * c);
+    }
+#pragma unroll
+    for (int ps = 0; ps < 6; ++ps)
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
+        rb[ps][u] = *reinterpret_cast<const uint4*>(sl + ps * plane + (size_t)(n0 + row) * ld + k0 + 8 * c);
+      }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
+      *reinterpret_cast<uint4*>(&As[buf][row * RS + 8 * c]) = ra[u];
+    }
+#pragma unroll
+    for (int ps = 0; ps < 6; ++ps)
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
+        *reinterpret_cast<uint4*>(&Bs[buf][ps][row * RS + 8 * c]) = rb[ps][u];
+      }
+  };
+
+  const int KT = ld / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+    bf8 a[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      a[i] = *reinterpret_cast<const bf8*>(&As[buf][(wm0 + i * 16 + lc) * RS + 8 * lr]);
+#pragma unroll
+    for (int ps = 0; ps < 6; ++ps) {
+      const int p = ps / 3;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bf8 b = *reinterpret_cast<const bf8*>(&Bs[buf][ps][(wn0 + j * 16 + lc) * RS + 8 * lr]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[p][i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < KT) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    float* X = p ? Xi : Xr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm0 + i * 16 + 4 * lr + r;
+          const int col = n0 + wn0 + j * 16 + lc;
+          X[(size_t)row * ld + col] = acc[p][i][j][r];
+        }
+  }
+}
+
+template <typename Fn>
+struct GemmCfg {
+  int bm, bn;
+  const char* name;
+  Fn fn;
+  int threads;
+};
+
+typedef void (*F64Fn)(const double*, const double*, const double*, double*, double*, int,
+                      const DevState*, int);
+typedef void (*F32Fn)(const float*, const float*, const float*, float*, float*, int,
+                      const DevState*, int);
+typedef void (*BFFn)(const uint16_t*, const uint16_t*, float*, float*, int, const DevState*, int);
+
+const GemmCfg<F64Fn> kF64[] = {
+    {64, 64, "f64_64x64_w32x32", k_gemm_k4<double, 64, 64, 32, 32>, 256},
+    {32, 32, "f64_32x32_w16x16", k_gemm_k4<double, 32, 32, 16, 16>, 256},
+    {128, 64, "f64_128x64_w64x32", k_gemm_k4<double, 128, 64, 64, 32>, 256},
+    {64, 128, "f64_64x128_w32x64", k_gemm_k4<double, 64, 128, 32, 64>, 256},
+    {64, 64, "f64_64x64_w64x32", k_gemm_k4<double, 64, 64, 64, 32>, 128},
+};
+const GemmCfg<F32Fn> kF32[] = {
+    {64, 64, "f32_64x64_w32x32", k_gemm_k4<float, 64, 64, 32, 32>, 256},
+    {32, 32, "f32_32x32_w32x32", k_gemm_k4<float, 32, 32, 32, 32>, 64},
+    {128, 64, "f32_128x64_w64x32", k_gemm_k4<float, 128, 64, 64, 32>, 256},
+    {64, 64, "f32_64x64_w64x32", k_gemm_k4<float, 64, 64, 64, 32>, 128},
+};
+const GemmCfg<BFFn> kBF[] = {
+    {64, 64, "bf16x3_64x64_w32x32", k_gemm_bf16x3<64, 64, 32, 32>, 256},
+    {32, 32, "bf16x3_32x32_w32x32", k_gemm_bf16x3<32, 32, 32, 32>, 64},
+    {64, 64, "bf16x3_64x64_w64x32", k_gemm_bf16x3<64, 64, 64, 32>, 128},
+    {128, 64, "bf16x3_128x64_w64x32", k_gemm_bf16x3<128, 64, 64, 32>, 256},
+};
+constexpr int kNumF64 = sizeof(kF64) / sizeof(kF64[0]);
+constexpr int kNumF32 = sizeof(kF32) / sizeof(kF32[0]);
+constexpr int kNumBF = sizeof(kBF) / sizeof(kBF[0]);
+
+}  // namespace
+
+int gemm_num_cfgs(int kind) {
+  return kind == OP_F64 ? kNumF64 : kind == OP_F32 ? kNumF32 : kind == OP_BF16X3 ? kNumBF : 0;
+}
+
+const char* gemm_cfg_name(int kind, int cfg) {
+  if (cfg < 0 || cfg >= gemm_num_cfgs(kind)) return "?";
+  return kind == OP_F64 ? kF64[cfg].name : kind == OP_F32 ? kF32[cfg].name : kBF[cfg].name;
+}
+
+int gemm_default_cfg(int kind, int n) {
+  (void)kind;
+  (void)n;
+  return 0;
+}
+
+template <typename C>
+static int pick(const C* table, int count, int cfg, int kind, int n, int ld) {
+  if (cfg < 0 || cfg >= count) cfg = gemm_default_cfg(kind, n);
+  if (ld % table[cfg].bm || ld % table[cfg].bn) cfg = 0;  // config 0 tiles 64x64
+  return cfg;
+}
+
+hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w, const double* yr,
+                       const double* yi, int gate, hipStream_t s) {
+  const int ld = P->ld;
+  if (kind == OP_F64) {
+    const auto& c = kF64[pick(kF64, kNumF64, cfg, kind, P->n, ld)];
+    hipLaunchKernelGGL(c.fn, dim3((ld / c.bm) * (ld / c.bn)), dim3(c.threads), 0, s, P->h_off, yr,
+                       yi, w.x_r, w.x_i, ld, w.st, gate);
+    return hipGetLastError();
+  }
+  if (kind == OP_F32) {
+    const auto& c = kF32[pick(kF32, kNumF32, cfg, kind, P->n, ld)];
+    hipLaunchKernelGGL(c.fn, dim3((ld / c.bm) * (ld / c.bn)), dim3(c.threads), 0, s,
+                       P->h_off_f32, (const float*)w.lo_r, (const float*)w.lo_i, w.xf_r, w.xf_i,
+                       ld, w.st, gate);
+    return hipGetLastError();
+  }
+  if (kind == OP_BF16X3) {
+    const auto& c = kBF[pick(kBF, kNumBF, cfg, kind, P->n, ld)];
+    hipLaunchKernelGGL(c.fn, dim3((ld / c.bm) * (ld / c.bn)), dim3(c.threads), 0, s,
+                       P->h_off_bf16, (const uint16_t*)w.sl, w.xf_r, w.xf_i, ld, w.st, gate);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qpr

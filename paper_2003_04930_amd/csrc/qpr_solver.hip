@@ -1,0 +1,555 @@
+// Host drivers of the C ABI: right-hand side, fixed RK4 steps and the
+// steady-state solve (plain FP64, or defect correction with a low-precision
+// product judged in FP64).
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "qpr_common.h"
+
+namespace qpr {
+
+namespace {
+thread_local char g_err[512] = "";
+
+constexpr double kRk4Limit = 2.8;  // inside RK4's stability region on both axes
+
+struct Pinned {  // two pinned host copies of the device control block
+  DevState* buf = nullptr;
+  Pinned() {
+    if (hipHostMalloc((void**)&buf, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+      buf = nullptr;
+  }
+};
+DevState* pinned_states() {
+  thread_local Pinned p;
+  return p.buf;
+}
+}  // namespace
+
+qpr_status fail(qpr_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+void clear_error() { g_err[0] = 0; }
+
+static int op_kind(int prec) {
+  return prec == QPR_FP32 ? OP_F32 : prec == QPR_BF16X3 ? OP_BF16X3 : OP_F64;
+}
+
+// ---------------------------------------------------------------- workspace
+namespace {
+struct WsLayout {
+  size_t yn, y1, y2, acc, x, ra, an, xf, lo, sl, pv, partials, st, scal, total;
+  int max_partials;
+};
+
+WsLayout ws_layout(int n, int prec) {
+  const size_t ld = (size_t)pad_n(n);
+  const size_t pd = ld * ld * 8, pf = ld * ld * 4, ph = ld * ld * 2;
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
+  L.yn = take(2 * pd);
+  L.y1 = take(2 * pd);
+  L.y2 = take(2 * pd);
+  L.acc = take(2 * pd);
+  L.x = take(2 * pd);
+  if (prec != QPR_FP64) {
+    L.ra = take(2 * pd);
+    L.an = take(2 * pd);
+    L.xf = take(2 * pf);
+    if (prec == QPR_FP32) L.lo = take(2 * pf);
+    if (prec == QPR_BF16X3) L.sl = take(6 * ph);
+  }
+  L.pv = take(4 * ld * 8);
+  const size_t tiles = (ld / 32) * (ld / 32);
+  L.max_partials = (int)std::max<size_t>(2 * tiles, 4 * 1024);
+  L.partials = take((size_t)L.max_partials * 8);
+  L.st = take(sizeof(DevState));
+  L.scal = take(16 * 8);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+size_t ws_bytes(int n, int prec) { return ws_layout(n, prec).total; }
+
+bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w) {
+  const WsLayout L = ws_layout(n, prec);
+  if (bytes < L.total) return false;
+  char* b = (char*)base;
+  const size_t ld = (size_t)pad_n(n);
+  const size_t pl = ld * ld;
+  w->n = n;
+  w->ld = (int)ld;
+  w->prec = prec;
+  w->yn_r = (double*)(b + L.yn);
+  w->yn_i = w->yn_r + pl;
+  w->y1_r = (double*)(b + L.y1);
+  w->y1_i = w->y1_r + pl;
+  w->y2_r = (double*)(b + L.y2);
+  w->y2_i = w->y2_r + pl;
+  w->acc_r = (double*)(b + L.acc);
+  w->acc_i = w->acc_r + pl;
+  w->x_r = (double*)(b + L.x);
+  w->x_i = w->x_r + pl;
+  if (prec != QPR_FP64) {
+    w->ra_r = (double*)(b + L.ra);
+    w->ra_i = w->ra_r + pl;
+    w->an_r = (double*)(b + L.an);
+    w->an_i = w->an_r + pl;
+    w->xf_r = (float*)(b + L.xf);
+    w->xf_i = w->xf_r + pl;
+    if (prec == QPR_FP32) {
+      w->lo_r = (float*)(b + L.lo);
+      w->lo_i = w->lo_r + pl;
+    }
+    if (prec == QPR_BF16X3) w->sl = (uint16_t*)(b + L.sl);
+  }
+  double* pv = (double*)(b + L.pv);
+  w->p_n = pv;
+  w->p_1 = pv + ld;
+  w->p_2 = pv + 2 * ld;
+  w->p_a = pv + 3 * ld;
+  w->partials = (double*)(b + L.partials);
+  w->max_partials = L.max_partials;
+  w->st = (DevState*)(b + L.st);
+  w->scal = (double*)(b + L.scal);
+  return true;
+}
+
+// ------------------------------------------------------------- validation
+static qpr_status check_problem(const qpr_problem* P) {
+  if (!P) return fail(QPR_E_ARG, "problem must not be NULL");
+  if (P->n < 2 || P->ld != pad_n(P->n) || !P->h_off || !P->d)
+    return fail(QPR_E_ARG, "problem struct is not a built problem");
+  return QPR_OK;
+}
+
+static qpr_status check_common(const qpr_problem* P, double omega, int prec, void* ws,
+                               size_t ws_bytes_, Ws* w) {
+  qpr_status st = check_problem(P);
+  if (st != QPR_OK) return st;
+  if (!(omega >= 0.0 && omega <= 1.0)) return fail(QPR_E_ARG, "omega must be in [0,1] (got %g)", omega);
+  if (prec != QPR_FP64 && prec != QPR_FP32 && prec != QPR_BF16X3)
+    return fail(QPR_E_ARG, "unknown precision %d", prec);
+  if (!ws) return fail(QPR_E_ARG, "workspace must not be NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(QPR_E_ARG, "workspace must be 256-byte aligned");
+  if (!ws_carve(ws, ws_bytes_, P->n, prec, w))
+    return fail(QPR_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes_,
+                ws_bytes(P->n, prec));
+  return QPR_OK;
+}
+
+static qpr_status check_dt(const qpr_problem* P, double omega, double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(QPR_E_ARG, "dt must be positive (got %g)", dt);
+  const double reach = dt * ((1.0 - omega) * (P->h_hi - P->h_lo) + 2.0 * omega);
+  if (reach >= kRk4Limit)
+    return fail(QPR_E_UNSTABLE,
+                "dt=%g outside the RK4 stability bound: dt*((1-w)*spread(H)+2w)=%.3f >= %.1f", dt,
+                reach, kRk4Limit);
+  return QPR_OK;
+}
+
+// ------------------------------------------------------------ one RK4 step
+// Enqueue the four stages of one step on the state (yn, p_n).  `xk` selects
+// the product; with a low-precision product the stage inputs are read from
+// the low-precision copies the previous epilogue wrote, and `ra` (the FP64
+// anchor residual) is added to every stage's right-hand side.
+static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView& pv, double omega,
+                               double dt, int xk, int cfg, int check, bool with_ra,
+                               hipStream_t s) {
+  const int gate = check == CHK_DELTA ? 1 : 0;
+  struct Stage {
+    double *inr, *ini, *pin, *outr, *outi, *pout;
+    double cdt;
+  };
+  const Stage stages[4] = {
+      {w.yn_r, w.yn_i, w.p_n, w.y1_r, w.y1_i, w.p_1, 0.5 * dt},
+      {w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, w.p_2, 0.5 * dt},
+      {w.y2_r, w.y2_i, w.p_2, w.y1_r, w.y1_i, w.p_1, dt},
+      {w.y1_r, w.y1_i, w.p_1, w.yn_r, w.yn_i, w.p_n, dt / 6.0},
+  };
+  for (int k = 0; k < 4; ++k) {
+    const Stage& sg = stages[k];
+    hipError_t e = launch_gemm(xk, cfg, P, w, sg.inr, sg.ini, gate, s);
+    if (e != hipSuccess) return e;
+    EpiArgs a{};
+    a.xr = w.x_r;
+    a.xi = w.x_i;
+    a.xfr = w.xf_r;
+    a.xfi = w.xf_i;
+    a.ysr = sg.inr;
+    a.ysi = sg.ini;
+    a.ps = sg.pin;
+    a.ynr = w.yn_r;
+    a.yni = w.yn_i;
+    a.accr = w.acc_r;
+    a.acci = w.acc_i;
+    a.outr = sg.outr;
+    a.outi = sg.outi;
+    a.pout = sg.pout;
+    a.rar = with_ra ? w.ra_r : nullptr;
+    a.rai = with_ra ? w.ra_i : nullptr;
+    a.lor = xk == OP_F32 ? w.lo_r : nullptr;
+    a.loi = xk == OP_F32 ? w.lo_i : nullptr;
+    a.slices = xk == OP_BF16X3 ? w.sl : nullptr;
+    a.omega = omega;
+    a.cdt = sg.cdt;
+    a.mode = EPI_S1 + k;
+    a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+    a.check = k == 0 ? check : CHK_NONE;
+    a.gate = gate;
+    e = launch_epilogue(pv, a, w, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// L(Y) for Y in (inr, ini, pin) into (outr, outi); FP64 product unless xk says otherwise.
+static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView& pv, double omega,
+                              double* inr, double* ini, double* pin, double* outr, double* outi,
+                              int xk, int cfg, int check, hipStream_t s) {
+  if (xk != OP_F64) {
+    hipError_t e = launch_to_lowp(xk, inr, ini, P->n, P->ld, w, s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_gemm(xk, cfg, P, w, inr, ini, 0, s);
+  if (e != hipSuccess) return e;
+  EpiArgs a{};
+  a.xr = w.x_r;
+  a.xi = w.x_i;
+  a.xfr = w.xf_r;
+  a.xfi = w.xf_i;
+  a.ysr = inr;
+  a.ysi = ini;
+  a.ps = pin;
+  a.outr = outr;
+  a.outi = outi;
+  a.omega = omega;
+  a.mode = EPI_RHS;
+  a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+  a.check = check;
+  return launch_epilogue(pv, a, w, s);
+}
+
+}  // namespace qpr
+
+using namespace qpr;
+
+extern "C" const char* qpr_last_error(void) { return g_err; }
+extern "C" const char* qpr_version(void) { return "qpr 0.1 (gfx950)"; }
+
+extern "C" size_t qpr_workspace_bytes(int32_t n, int32_t prec) {
+  if (n < 2 || (prec != QPR_FP64 && prec != QPR_FP32 && prec != QPR_BF16X3)) return 0;
+  return ws_bytes(n, prec);
+}
+
+extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho, double* out,
+                              int32_t prec, void* ws, size_t wsb, qpr_stream_t stream) {
+  clear_error();
+  Ws w;
+  qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
+  if (st != QPR_OK) return st;
+  if (!rho || !out) return fail(QPR_E_ARG, "rho and out must not be NULL");
+  if (rho == out) return fail(QPR_E_ARG, "rho and out must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  const ProbView pv = view_of(P);
+  QPR_HIP(launch_state_init(w.st, 0.0, 0, 0, s));
+  QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
+  QPR_HIP(enqueue_rhs(P, w, pv, omega, w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, op_kind(prec), -1,
+                        CHK_NONE, s));
+  QPR_HIP(launch_pad_out(w.y2_r, w.y2_i, P->n, P->ld, out, s));
+  return QPR_OK;
+}
+
+extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt, int32_t nsteps,
+                                   double* rho, int32_t prec, double* diag_out, void* ws,
+                                   size_t wsb, qpr_stream_t stream) {
+  clear_error();
+  Ws w;
+  qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
+  if (st != QPR_OK) return st;
+  if (!rho) return fail(QPR_E_ARG, "rho must not be NULL");
+  if (nsteps < 0) return fail(QPR_E_ARG, "nsteps must be >= 0");
+  if ((st = check_dt(P, omega, dt)) != QPR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const ProbView pv = view_of(P);
+  const int xk = op_kind(prec);
+  QPR_HIP(launch_state_init(w.st, 0.0, nsteps, 0, s));
+  QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
+  if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.yn_r, w.yn_i, P->n, P->ld, w, s));
+  for (int k = 0; k < nsteps; ++k)
+    QPR_HIP(enqueue_step(P, w, pv, omega, dt, xk, -1, CHK_NONE, false, s));
+  if (diag_out) {
+    QPR_HIP(launch_state_stats(w.yn_r, w.yn_i, w.p_n, P->n, P->ld, w, s));
+    // diag_out = [resid2, trace, herm, nonfinite]
+    QPR_HIP(hipMemcpyAsync(diag_out, &w.st->resid2, 8, hipMemcpyDeviceToDevice, s));
+    QPR_HIP(hipMemcpyAsync(diag_out + 1, &w.st->aux[0], 16, hipMemcpyDeviceToDevice, s));
+    QPR_HIP(hipMemcpyAsync(diag_out + 3, &w.st->aux[3], 8, hipMemcpyDeviceToDevice, s));
+  }
+  QPR_HIP(launch_pad_out(w.yn_r, w.yn_i, P->n, P->ld, rho, s));
+  return QPR_OK;
+}
+
+namespace {
+
+// Run chunks of `chunk` steps (eager or as a replayed graph) until the device
+// control block says stop.  Returns the final host copy of the block.
+qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chunk,
+                      DevState* dev_st, bool use_graph, hipStream_t s, DevState* final_state,
+                      long long* chunks_run) {
+  DevState* hs = pinned_states();
+  if (!hs) return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cs = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  qpr_status rc = QPR_OK;
+  auto cleanup = [&]() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (cs) hipStreamDestroy(cs);
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
+  };
+#define QPR_HIP_C(call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      rc = fail(QPR_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));              \
+      cleanup();                                                                        \
+      return rc;                                                                        \
+    }                                                                                   \
+  } while (0)
+  if (use_graph) {
+    QPR_HIP_C(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    QPR_HIP_C(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_chunk(cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    QPR_HIP_C(e);
+    QPR_HIP_C(e2);
+    QPR_HIP_C(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  QPR_HIP_C(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  QPR_HIP_C(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  auto launch = [&](int slot) -> hipError_t {
+    hipError_t e = use_graph ? hipGraphLaunch(exec, s) : enqueue_chunk(s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&hs[slot], dev_st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(ev[slot], s);
+  };
+  long long c = 0;
+  QPR_HIP_C(launch(0));
+  for (;;) {
+    QPR_HIP_C(launch((int)((c + 1) & 1)));  // keep one chunk in flight
+    QPR_HIP_C(hipEventSynchronize(ev[c & 1]));
+    const DevState cur = hs[c & 1];
+    ++c;
+    if (cur.stop) break;
+  }
+  QPR_HIP_C(hipStreamSynchronize(s));
+  *final_state = hs[c & 1];  // state after the in-flight chunk (a no-op once stopped)
+  *chunks_run = c + 1;
+  cleanup();
+#undef QPR_HIP_C
+  return QPR_OK;
+}
+
+}  // namespace
+
+extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt, double tol,
+                                       int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
+                                       qpr_stats* stats, const qpr_opts* opts, void* ws,
+                                       size_t wsb, qpr_stream_t stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  clear_error();
+  Ws w;
+  qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
+  if (st != QPR_OK) return st;
+  if (!rho) return fail(QPR_E_ARG, "rho must not be NULL");
+  if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive (got %g)", tol);
+  if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
+  if ((st = check_dt(P, omega, dt)) != QPR_OK) return st;
+  qpr_opts o{64, 1, 0, 1, -1, {0, 0, 0}};
+  if (opts) o = *opts;
+  if (o.chunk <= 0) o.chunk = 64;
+  if (o.fold_every <= 0) o.fold_every = o.chunk;
+  hipStream_t s = (hipStream_t)stream;
+  const ProbView pv = view_of(P);
+  const int n = P->n, ld = P->ld;
+  qpr_stats S{};
+  qpr_status result = QPR_OK;
+
+  const bool graph = o.use_graph != 0;
+  DevState fs{};
+  long long chunks = 0;
+  double* out_r = w.yn_r;
+  double* out_i = w.yn_i;
+  double* out_p = w.p_n;
+  if (prec == QPR_FP64) {
+    QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_PLAIN, s));
+    QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
+    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
+      for (int k = 0; k < o.chunk; ++k) {
+        hipError_t e = enqueue_step(P, w, pv, omega, dt, OP_F64, o.gemm_cfg, CHK_PLAIN, false, q);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    if (st != QPR_OK) return st;
+    S.steps = fs.converged ? fs.conv_step : fs.step;
+    S.rhs_evals = 4 * S.steps + 1;
+    S.rhs_evals_fp64 = S.rhs_evals;
+    S.residual = std::sqrt(fs.resid2);
+  } else {
+    // Defect correction: anchor rho_a (FP64) with residual r_a = L(rho_a) in
+    // FP64; delta follows d delta/dt = r_a + L_lowp(delta) from delta = 0 and
+    // is folded into the anchor every fold_every steps (or as soon as the
+    // running estimate meets the tolerance), after which r_a is recomputed in
+    // FP64 and judged.
+    const int xk = op_kind(prec);
+    out_r = w.an_r;
+    out_i = w.an_i;
+    out_p = w.p_a;
+    const size_t plane = (size_t)ld * ld;
+    auto reset_delta = [&](hipStream_t q) -> hipError_t {
+      hipError_t e = launch_fill(w.yn_r, 2 * plane * 8, q);
+      if (e == hipSuccess) e = launch_fill(w.p_n, (size_t)ld * 8, q);
+      if (e == hipSuccess && xk == OP_F32) e = launch_fill(w.lo_r, 2 * plane * 4, q);
+      if (e == hipSuccess && xk == OP_BF16X3) e = launch_fill(w.sl, 6 * plane * 2, q);
+      return e;
+    };
+    auto fold_judge = [&](hipStream_t q, bool first) -> hipError_t {
+      hipError_t e = hipSuccess;
+      if (!first) e = launch_axpy_planes(w.an_r, w.an_i, w.yn_r, w.yn_i, 1.0, n, ld, w.p_a, w.st, q);
+      if (e == hipSuccess && o.renorm) e = launch_trace(w.p_a, n, w.st, q);
+      if (e == hipSuccess && o.renorm) e = launch_scale_planes(w.an_r, w.an_i, w.p_a, n, ld, w.st, q);
+      if (e == hipSuccess)
+        e = enqueue_rhs(P, w, pv, omega, w.an_r, w.an_i, w.p_a, w.ra_r, w.ra_i, OP_F64,
+                        o.gemm_cfg, CHK_JUDGE, q);
+      if (e == hipSuccess) e = reset_delta(q);
+      return e;
+    };
+    QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_DELTA, s));
+    QPR_HIP(launch_pad_in(rho, n, ld, w.an_r, w.an_i, w.p_a, s));
+    QPR_HIP(fold_judge(s, true));
+    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
+      for (int k = 0; k < o.fold_every; ++k) {
+        hipError_t e = enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, CHK_DELTA, true, q);
+        if (e != hipSuccess) return e;
+      }
+      return fold_judge(q, false);
+    };
+    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    if (st != QPR_OK) return st;
+    S.steps = fs.converged ? fs.conv_step : fs.step;
+    S.folds = fs.folds;
+    S.rhs_evals_fp64 = fs.folds;
+    S.rhs_evals = 4 * S.steps + fs.folds;
+    S.residual = std::sqrt(fs.judge2);
+  }
+  S.converged = fs.converged;
+  if (fs.nonfinite) result = fail(QPR_E_NONFINITE, "non-finite value in the state or L(rho)");
+  else if (!fs.converged)
+    result = fail(QPR_E_NOT_CONVERGED, "not converged after %lld steps (residual %.3e)",
+                  (long long)S.steps, S.residual);
+
+  if (result == QPR_OK || result == QPR_E_NOT_CONVERGED) {
+    QPR_HIP(launch_state_stats(out_r, out_i, out_p, n, ld, w, s));
+    DevState hs{};
+    QPR_HIP(hipMemcpyAsync(&hs, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    QPR_HIP(launch_pad_out(out_r, out_i, n, ld, rho, s));
+    if (rank && result == QPR_OK) QPR_HIP(launch_rank(n, out_p, rank, s));
+    QPR_HIP(hipStreamSynchronize(s));
+    S.trace_err = std::fabs(hs.aux[0] - 1.0);
+    S.herm_err = hs.aux[1];
+    S.min_diag = hs.aux[2];
+  }
+  S.t = (double)S.steps * dt;
+  S.status = result;
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = S;
+  return result;
+}
+
+extern "C" qpr_status qpr_rank(int32_t n, const double* p, int32_t* order, qpr_stream_t stream) {
+  clear_error();
+  if (n < 1) return fail(QPR_E_ARG, "n must be >= 1");
+  if (!p || !order) return fail(QPR_E_ARG, "p and order must not be NULL");
+  QPR_HIP(launch_rank(n, p, order, (hipStream_t)stream));
+  return QPR_OK;
+}
+
+extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32_t prec,
+                                       int32_t cfg, int32_t reps, const double* rho,
+                                       double* ms_out, void* ws, size_t wsb,
+                                       qpr_stream_t stream) {
+  clear_error();
+  Ws w;
+  qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
+  if (st != QPR_OK) return st;
+  if (!rho || !ms_out) return fail(QPR_E_ARG, "rho and ms_out must not be NULL");
+  if (reps < 1) return fail(QPR_E_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const ProbView pv = view_of(P);
+  const int xk = op_kind(prec);
+  QPR_HIP(launch_state_init(w.st, 0.0, 0, CHK_NONE, s));
+  QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
+  if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
+  EpiArgs a{};
+  a.xr = w.x_r;
+  a.xi = w.x_i;
+  a.xfr = w.xf_r;
+  a.xfi = w.xf_i;
+  a.ysr = w.y1_r;
+  a.ysi = w.y1_i;
+  a.ps = w.p_1;
+  a.ynr = w.y1_r;
+  a.yni = w.y1_i;
+  a.accr = w.acc_r;
+  a.acci = w.acc_i;
+  a.outr = w.y2_r;
+  a.outi = w.y2_i;
+  a.pout = w.p_2;
+  a.omega = omega;
+  a.cdt = 0.005;
+  a.mode = EPI_S1;  // the stage-1 pass: five plane reads, four plane writes, reduction
+  a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+  a.lor = xk == OP_F32 ? w.lo_r : nullptr;
+  a.loi = xk == OP_F32 ? w.lo_i : nullptr;
+  a.slices = xk == OP_BF16X3 ? w.sl : nullptr;
+  a.check = CHK_NONE;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev) QPR_HIP(hipEventCreate(&e));
+  for (int r = 0; r < 3; ++r) QPR_HIP(launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s));
+  QPR_HIP(hipEventRecord(ev[0], s));
+  for (int r = 0; r < reps; ++r) QPR_HIP(launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s));
+  QPR_HIP(hipEventRecord(ev[1], s));
+  for (int r = 0; r < reps; ++r) QPR_HIP(launch_epilogue(pv, a, w, s));
+  QPR_HIP(hipEventRecord(ev[2], s));
+  QPR_HIP(hipEventSynchronize(ev[2]));
+  float t0 = 0.f, t1 = 0.f;
+  QPR_HIP(hipEventElapsedTime(&t0, ev[0], ev[1]));
+  QPR_HIP(hipEventElapsedTime(&t1, ev[1], ev[2]));
+  for (auto& e : ev) hipEventDestroy(e);
+  ms_out[0] = (double)t0 / reps;
+  ms_out[1] = (double)t1 / reps;
+  return QPR_OK;
+}
+
+extern "C" int32_t qpr_product_configs(int32_t prec) { return gemm_num_cfgs(op_kind(prec)); }
+
+extern "C" const char* qpr_product_config_name(int32_t prec, int32_t cfg) {
+  return gemm_cfg_name(op_kind(prec), cfg);
+}

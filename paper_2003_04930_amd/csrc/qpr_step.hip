@@ -1,0 +1,562 @@
+// Fused right-hand-side epilogue and the small per-step kernels.
+//
+// Right-hand side of Eq. (1) (GKSL anticommutator, jump operators
+// sqrt(G_ij)|i><j| for all ordered pairs) in the real planes R = Re Y,
+// I = Im Y, with X = H_off Y = A + iB from the product kernel and h = diag H:
+//
+//   Re L_ab = (1-w) [ B_ab + B_ba + (h_a - h_b) I_ab ] + w [ delta_ab g_a - (d_a + d_b)/2 R_ab ]
+//   Im L_ab = (1-w) [ A_ba - A_ab - (h_a - h_b) R_ab ] - w (d_a + d_b)/2 I_ab
+//
+// where g = G diag(Y) is the gain of the jump terms (sum_k L_k Y L_k^dag =
+// diag(G p)) and d_j = sum_i G_ij (sum_k L_k^dag L_k = diag(d)).  Every term
+// is odd or even under (a,b) -> (b,a) exactly as written, so a Hermitian Y
+// gives a bitwise Hermitian L.
+//
+// The same pass applies the classical RK4 stage update of Supplementary
+// Note 2 (k_s = L(Y_s); Y_{s+1} = y_n + c_s dt k_s; acc accumulates k with
+// weights 1,2,2,1; y_{n+1} = y_n + dt/6 (acc + k_4)), reduces ||k_1||_F^2 and a
+// non-finite flag with a deterministic two-level reduction, and (stage 1)
+// decides convergence on the device.
+#include <cmath>
+#include <cstdio>
+
+#include "qpr_common.h"
+#include "qpr_device.h"
+
+namespace qpr {
+
+namespace {
+
+constexpr int TE = 32;       // epilogue tile edge
+constexpr int ETHREADS = 256;
+
+__device__ __forceinline__ uint16_t bf16_rn(float f) {
+  // round-to-nearest-even float -> bf16 (inputs are finite here)
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double bf16_to_d(uint16_t h) {
+  return (double)__uint_as_float(((unsigned int)h) << 16);
+}
+
+// Three bf16 slices s1 + s2 + s3 of v (each the bf16 rounding of what the
+// previous slices leave), the residuals taken exactly in FP64.
+__device__ __forceinline__ void split3(double v, uint16_t& s1, uint16_t& s2, uint16_t& s3) {
+  s1 = bf16_rn((float)v);
+  const double r1 = v - bf16_to_d(s1);
+  s2 = bf16_rn((float)r1);
+  const double r2 = r1 - bf16_to_d(s2);
+  s3 = bf16_rn((float)r2);
+}
+
+__device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double* partials,
+                                               DevState* st, double* red, int* flag,
+                                               double& tot, int& bad) {
+  const int tid = threadIdx.x;
+  const int nb = gridDim.x;
+  double s = block_sum(my_sum, red, ETHREADS / 64);
+  int b = __syncthreads_or(my_bad);
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = (double)b;
+    __threadfence();
+    const unsigned int t = atomicAdd(&st->ticket, 1u);
+    *flag = (t == (unsigned int)(nb - 1));
+  }
+  __syncthreads();
+  tot = 0.0;
+  bad = 0;
+  if (*flag) {
+    __threadfence();
+    double acc = 0.0, bb = 0.0;
+    for (int i = tid; i < nb; i += ETHREADS) {
+      acc += partials[2 * i];
+      bb = fmax(bb, partials[2 * i + 1]);
+    }
+    tot = block_sum(acc, red, ETHREADS / 64);
+    bad = __syncthreads_or(bb != 0.0);
+  }
+}
+
+template <int XK>
+__global__ void __launch_bounds__(ETHREADS)
+    k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
+  if (st->stop || (a.gate && st->hold)) return;
+  __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
+  __shared__ double gs[TE];
+  __shared__ double red[ETHREADS / 64];
+  __shared__ int flag;
+  const int tid = threadIdx.x, tx = tid & (TE - 1), ty = tid / TE;
+  const int n = pv.n, ld = pv.ld;
+  const int tiles = ld / TE;
+  const int I = blockIdx.x % tiles, J = blockIdx.x / tiles;
+  const int a0 = I * TE, b0 = J * TE;
+
+  // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
+#pragma unroll
+  for (int m = 0; m < TE / 8; ++m) {
+    const int r = ty + 8 * m;
+    const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
+    if (XK == OP_F64) {
+      Tr[r][tx] = a.xr[o];
+      Ti[r][tx] = a.xi[o];
+    } else {
+      Tr[r][tx] = (double)a.xfr[o];
+      Ti[r][tx] = (double)a.xfi[o];
+    }
+  }
+  if (I == J) {  // gain of the jump terms on this tile's diagonal
+    double sp = 0.0, sd = 0.0;
+    for (int j = tid; j < n; j += ETHREADS) {
+      const double v = a.ps[j];
+      sp += v;
+      sd += pv.dangling[j] ? v : 0.0;
+    }
+    const double P = block_sum(sp, red, ETHREADS / 64);
+    const double D = block_sum(sd, red, ETHREADS / 64);
+    if (tid < TE && a0 + tid < n) {
+      GainView gv{n, pv.teleport, pv.alpha, pv.inv_outdeg, pv.dangling, pv.in_ptr, pv.in_idx};
+      gs[tid] = gain_row(gv, a0 + tid, a.ps, P, D);
+    }
+  }
+  __syncthreads();
+
+  const double w = a.omega, cw = 1.0 - a.omega;
+  const int b = b0 + tx;
+  const bool bin = b < n;
+  const double hb = bin ? pv.h[b] : 0.0, db = bin ? pv.d[b] : 0.0;
+  double ssum = 0.0;
+  int sbad = 0;
+#pragma unroll
+  for (int m = 0; m < TE / 8; ++m) {
+    const int r = ty + 8 * m;
+    const int ar = a0 + r;
+    const size_t o = (size_t)ar * ld + b;
+    double kr = 0.0, ki = 0.0;
+    const bool inside = bin && ar < n;
+    if (inside) {
+      double A_ab, B_ab;
+      if (XK == OP_F64) {
+        A_ab = a.xr[o];
+        B_ab = a.xi[o];
+      } else {
+        A_ab = (double)a.xfr[o];
+        B_ab = (double)a.xfi[o];
+      }
+      const double A_ba = Tr[tx][r], B_ba = Ti[tx][r];
+      const double R = a.ysr[o], Im = a.ysi[o];
+      const double hab = pv.h[ar] - hb;
+      const double dab = 0.5 * (pv.d[ar] + db);
+      const double gd = (ar == b) ? gs[r] : 0.0;
+      kr = cw * ((B_ab + B_ba) + hab * Im) + w * (gd - dab * R);
+      ki = cw * ((A_ba - A_ab) - hab * R) - w * (dab * Im);
+      if (a.rar) {
+        kr += a.rar[o];
+        ki += a.rai[o];
+      }
+      ssum += kr * kr + ki * ki;
+      sbad |= !(isfinite(kr) && isfinite(ki));
+    }
+    double outr, outi;
+    switch (a.mode) {
+      case EPI_RHS:
+        outr = kr;
+        outi = ki;
+        break;
+      case EPI_S1:
+        a.accr[o] = kr;
+        a.acci[o] = ki;
+        outr = a.ynr[o] + a.cdt * kr;
+        outi = a.yni[o] + a.cdt * ki;
+        break;
+      case EPI_S2:
+      case EPI_S3:
+        a.accr[o] += 2.0 * kr;
+        a.acci[o] += 2.0 * ki;
+        outr = a.ynr[o] + a.cdt * kr;
+        outi = a.yni[o] + a.cdt * ki;
+        break;
+      default:  // EPI_S4: y_{n+1} = y_n + dt/6 (acc + k4)
+        outr = a.ynr[o] + a.cdt * (a.accr[o] + kr);
+        outi = a.yni[o] + a.cdt * (a.acci[o] + ki);
+        break;
+    }
+    if (!inside) {
+      outr = 0.0;
+      outi = 0.0;
+    }
+    a.outr[o] = outr;
+    a.outi[o] = outi;
+    if (a.pout && inside && ar == b) a.pout[ar] = outr;
+    if (a.lor) {
+      a.lor[o] = (float)outr;
+      a.loi[o] = (float)outi;
+    }
+    if (a.slices) {
+      const size_t plane = (size_t)ld * ld;
+      uint16_t s1, s2, s3;
+      split3(outr, s1, s2, s3);
+      a.slices[o] = s1;
+      a.slices[plane + o] = s2;
+      a.slices[2 * plane + o] = s3;
+      // imaginary plane stored negated: row b of -I is column b of I
+      split3(-outi, s1, s2, s3);
+      a.slices[3 * plane + o] = s1;
+      a.slices[4 * plane + o] = s2;
+      a.slices[5 * plane + o] = s3;
+    }
+  }
+
+  if (a.mode == EPI_S1 || a.mode == EPI_RHS) {
+    double tot;
+    int bad;
+    last_block_sum(ssum, sbad, partials, st, red, &flag, tot, bad);
+    if (flag && tid == 0) {
+      st->resid2 = tot;
+      st->rhs_evals += 1;
+      if (bad) {
+        st->nonfinite = 1;
+        st->stop = 1;
+      } else if (a.check == CHK_PLAIN) {
+        if (tot < st->tol2) {
+          st->converged = 1;
+          st->conv_step = st->step;
+          st->stop = 1;
+        } else if (st->step >= st->max_steps) {
+          st->stop = 1;
+        } else {
+          st->step += 1;
+        }
+      } else if (a.check == CHK_DELTA) {
+        // ||r_a + L_lowp(delta)|| estimates the residual of rho_a + delta:
+        // once it meets 0.9 tol (or the step budget is spent) hold further
+        // steps so the FP64 fold and judge run.
+        if (tot < 0.81 * st->tol2 || st->step >= st->max_steps) st->hold = 1;
+        else st->step += 1;
+      } else if (a.check == CHK_JUDGE) {
+        st->judge2 = tot;
+        st->folds += 1;
+        if (tot < st->tol2) {
+          st->converged = 1;
+          st->conv_step = st->step;
+          st->stop = 1;
+        } else if (st->step >= st->max_steps) {
+          st->stop = 1;
+        } else {
+          st->hold = 0;
+        }
+      }
+      st->ticket = 0u;
+    }
+  }
+}
+
+// planar n x n (unpadded) -> ld x ld planes with zero padding, p = Re diag
+__global__ void k_pad_in(const double* __restrict__ rho, int n, int ld, double* __restrict__ r,
+                         double* __restrict__ im, double* __restrict__ p) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tot = (size_t)ld * ld;
+  if (idx >= tot) return;
+  const int a = (int)(idx / ld), b = (int)(idx % ld);
+  double vr = 0.0, vi = 0.0;
+  if (a < n && b < n) {
+    vr = rho[(size_t)a * n + b];
+    vi = rho[(size_t)n * n + (size_t)a * n + b];
+  }
+  r[idx] = vr;
+  im[idx] = vi;
+  if (p && a == b && a < n) p[a] = vr;
+}
+
+__global__ void k_pad_out(const double* __restrict__ r, const double* __restrict__ im, int n,
+                          int ld, double* __restrict__ rho) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tot = (size_t)n * n;
+  if (idx >= tot) return;
+  const int a = (int)(idx / n), b = (int)(idx % n);
+  rho[idx] = r[(size_t)a * ld + b];
+  rho[tot + idx] = im[(size_t)a * ld + b];
+}
+
+__global__ void k_to_f32(const double* __restrict__ r, const double* __restrict__ im, size_t tot,
+                         float* __restrict__ fr, float* __restrict__ fi) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  fr[idx] = (float)r[idx];
+  fi[idx] = (float)im[idx];
+}
+
+__global__ void k_to_bf16x3(const double* __restrict__ r, const double* __restrict__ im,
+                            size_t tot, uint16_t* __restrict__ sl) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  uint16_t s1, s2, s3;
+  split3(r[idx], s1, s2, s3);
+  sl[idx] = s1;
+  sl[tot + idx] = s2;
+  sl[2 * tot + idx] = s3;
+  split3(-im[idx], s1, s2, s3);
+  sl[3 * tot + idx] = s1;
+  sl[4 * tot + idx] = s2;
+  sl[5 * tot + idx] = s3;
+}
+
+__global__ void k_state_init(DevState* st, double tol, long long max_steps, int check) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->resid2 = 0.0;
+  st->tol2 = tol * tol;
+  st->step = 0;
+  st->max_steps = max_steps;
+  st->conv_step = -1;
+  st->rhs_evals = 0;
+  st->stop = 0;
+  st->converged = 0;
+  st->nonfinite = 0;
+  st->check = check;
+  st->ticket = 0u;
+  st->hold = 0;
+  st->judge2 = 0.0;
+  st->folds = 0;
+  for (int i = 0; i < 8; ++i) st->aux[i] = 0.0;
+}
+
+// st->aux[0] = sum_a p_a (one workgroup, fixed order); skipped once stopped
+__global__ void __launch_bounds__(1024) k_trace(const double* __restrict__ p, int n,
+                                                DevState* __restrict__ st) {
+  __shared__ double red[16];
+  if (st->stop) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += p[i];
+  s = block_sum_1024(s, red);
+  if (threadIdx.x == 0) st->aux[0] = s;
+}
+
+// Final-state diagnostics: trace, max |Y - Y^dag|, min diag, non-finite.
+// Partial results per block, then the last block folds them into st->aux:
+// aux[0] = tr, aux[1] = herm err, aux[2] = min diag, aux[3] = non-finite.
+__global__ void __launch_bounds__(256) k_state_stats(const double* __restrict__ r,
+                                                     const double* __restrict__ im,
+                                                     const double* __restrict__ p, int n, int ld,
+                                                     DevState* st, double* partials) {
+  __shared__ double red[4];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const size_t tot = (size_t)n * n;
+  double herm = 0.0;
+  int bad = 0;
+  for (size_t idx = (size_t)blockIdx.x * 256 + tid; idx < tot; idx += (size_t)gridDim.x * 256) {
+    const int a = (int)(idx / n), b = (int)(idx % n);
+    const double xr = r[(size_t)a * ld + b], xi = im[(size_t)a * ld + b];
+    const double yr = r[(size_t)b * ld + a], yi = im[(size_t)b * ld + a];
+    herm = fmax(herm, fmax(fabs(xr - yr), fabs(xi + yi)));
+    bad |= !(isfinite(xr) && isfinite(xi));
+  }
+  double tr = 0.0, mn = 1e300;
+  for (int i = (int)blockIdx.x * 256 + tid; i < n; i += gridDim.x * 256) {
+    tr += p[i];
+    mn = fmin(mn, p[i]);
+  }
+  // block reductions (fixed order)
+  tr = block_sum(tr, red, 4);
+  herm = wave_max_d(herm);
+  mn = wave_min_d(mn);
+  __shared__ double hm[4], mm[4];
+  if ((tid & 63) == 0) {
+    hm[tid >> 6] = herm;
+    mm[tid >> 6] = mn;
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) {
+    double h = 0.0, m = 1e300;
+    for (int w = 0; w < 4; ++w) {
+      h = fmax(h, hm[w]);
+      m = fmin(m, mm[w]);
+    }
+    partials[4 * blockIdx.x + 0] = tr;
+    partials[4 * blockIdx.x + 1] = h;
+    partials[4 * blockIdx.x + 2] = m;
+    partials[4 * blockIdx.x + 3] = bad;
+    __threadfence();
+    const unsigned int t = atomicAdd(&st->ticket, 1u);
+    flag = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (flag && tid == 0) {
+    __threadfence();
+    double T = 0.0, Hm = 0.0, Mn = 1e300, B = 0.0;
+    for (unsigned int i = 0; i < gridDim.x; ++i) {
+      T += partials[4 * i + 0];
+      Hm = fmax(Hm, partials[4 * i + 1]);
+      Mn = fmin(Mn, partials[4 * i + 2]);
+      B = fmax(B, partials[4 * i + 3]);
+    }
+    st->aux[0] = T;
+    st->aux[1] = Hm;
+    st->aux[2] = Mn;
+    st->aux[3] = B;
+    st->ticket = 0u;
+  }
+}
+
+// Rank by counting: position of i = #{j : p_j > p_i or (p_j == p_i and j < i)}.
+__global__ void __launch_bounds__(256) k_rank(int n, const double* __restrict__ p,
+                                              int* __restrict__ order) {
+  __shared__ double ps[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double pi = i < n ? p[i] : 0.0;
+  int cnt = 0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    const int j = j0 + threadIdx.x;
+    ps[threadIdx.x] = j < n ? p[j] : 0.0;
+    __syncthreads();
+    const int lim = min(256, n - j0);
+    for (int t = 0; t < lim; ++t) {
+      const double q = ps[t];
+      cnt += (q > pi) || (q == pi && j0 + t < i);
+    }
+    __syncthreads();
+  }
+  if (i < n) order[cnt] = i;
+}
+
+__global__ void k_axpy_planes(double* __restrict__ yr, double* __restrict__ yi,
+                              const double* __restrict__ xr, const double* __restrict__ xi,
+                              double alpha, int n, int ld, double* __restrict__ p,
+                              const DevState* __restrict__ st) {
+  if (st && st->stop) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ld * ld) return;
+  const double vr = yr[idx] + alpha * xr[idx];
+  yr[idx] = vr;
+  yi[idx] = yi[idx] + alpha * xi[idx];
+  const int a = (int)(idx / ld), b = (int)(idx % ld);
+  if (p && a == b && a < n) p[a] = vr;
+}
+
+// y <- y / tr, tr = st->aux[0]
+__global__ void k_scale_planes(double* __restrict__ r, double* __restrict__ im,
+                               double* __restrict__ p, int n, int ld,
+                               const DevState* __restrict__ st) {
+  if (st->stop) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ld * ld) return;
+  const double inv = 1.0 / st->aux[0];
+  const double vr = r[idx] * inv;
+  r[idx] = vr;
+  im[idx] = im[idx] * inv;
+  const int a = (int)(idx / ld), b = (int)(idx % ld);
+  if (p && a == b && a < n) p[a] = vr;
+}
+
+__global__ void k_fill16(uint4* dst, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+__global__ void k_fill1(unsigned char* dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0;
+}
+
+inline int blocks_for(size_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+ProbView view_of(const qpr_problem* P) {
+  return ProbView{P->n, P->ld, P->teleport, P->alpha, P->h_diag, P->d, P->inv_outdeg,
+                  P->dangling, P->in_ptr, P->in_idx};
+}
+
+hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s) {
+  const int tiles = pv.ld / TE;
+  const int grid = tiles * tiles;
+  if (grid * 2 > w.max_partials) return hipErrorInvalidValue;
+  if (a.xkind == OP_F64)
+    k_epilogue<OP_F64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  else
+    k_epilogue<OP_F32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_in(const double* rho, int n, int ld, double* r, double* i, double* p,
+                         hipStream_t s) {
+  const size_t tot = (size_t)ld * ld;
+  k_pad_in<<<blocks_for(tot, 256), 256, 0, s>>>(rho, n, ld, r, i, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_out(const double* r, const double* i, int n, int ld, double* rho,
+                          hipStream_t s) {
+  const size_t tot = (size_t)n * n;
+  k_pad_out<<<blocks_for(tot, 256), 256, 0, s>>>(r, i, n, ld, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_lowp(int kind, const double* r, const double* i, int n, int ld, const Ws& w,
+                          hipStream_t s) {
+  (void)n;
+  const size_t tot = (size_t)ld * ld;
+  if (kind == OP_F32)
+    k_to_f32<<<blocks_for(tot, 256), 256, 0, s>>>(r, i, tot, w.lo_r, w.lo_i);
+  else if (kind == OP_BF16X3)
+    k_to_bf16x3<<<blocks_for(tot, 256), 256, 0, s>>>(r, i, tot, w.sl);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(DevState* st, double tol, long long max_steps, int check,
+                             hipStream_t s) {
+  k_state_init<<<1, 64, 0, s>>>(st, tol, max_steps, check);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_stats(const double* r, const double* i, const double* p, int n, int ld,
+                              const Ws& w, hipStream_t s) {
+  int grid = blocks_for((size_t)n * n, 256);
+  grid = grid > 1024 ? 1024 : grid;
+  if (grid * 4 > w.max_partials) grid = w.max_partials / 4;
+  k_state_stats<<<grid, 256, 0, s>>>(r, i, p, n, ld, w.st, w.partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank(int n, const double* p, int* order, hipStream_t s) {
+  k_rank<<<blocks_for((size_t)n, 256), 256, 0, s>>>(n, p, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_planes(double* yr, double* yi, const double* xr, const double* xi, double a,
+                              int n, int ld, double* p, const DevState* st, hipStream_t s) {
+  k_axpy_planes<<<blocks_for((size_t)ld * ld, 256), 256, 0, s>>>(yr, yi, xr, xi, a, n, ld, p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const double* p, int n, DevState* st, hipStream_t s) {
+  k_trace<<<1, 1024, 0, s>>>(p, n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_planes(double* r, double* i, double* p, int n, int ld,
+                               const DevState* st, hipStream_t s) {
+  k_scale_planes<<<blocks_for((size_t)ld * ld, 256), 256, 0, s>>>(r, i, p, n, ld, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* dst, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (((uintptr_t)dst % 16) == 0 && bytes % 16 == 0) {
+    const size_t n16 = bytes / 16;
+    int grid = blocks_for(n16, 256);
+    grid = grid > 4096 ? 4096 : grid;
+    k_fill16<<<grid, 256, 0, s>>>((uint4*)dst, n16);
+  } else {
+    int grid = blocks_for(bytes, 256);
+    grid = grid > 4096 ? 4096 : grid;
+    k_fill1<<<grid, 256, 0, s>>>((unsigned char*)dst, bytes);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qpr

@@ -1,0 +1,420 @@
+"""Python binding of libqpr (ctypes).  Argument marshalling only.
+
+Every numerical step runs in the HIP library; PyTorch supplies device memory
+(problem arenas, workspaces, density matrices) and the current stream.  The
+library is loaded on first use and a missing library raises
+:class:`QprError` -- there is no CPU fallback.
+
+Density matrices are planar float64 tensors of shape (2, n, n) on the GPU:
+``rho[0] = Re rho``, ``rho[1] = Im rho`` (row-major, rho_ab = <a|rho|b>).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqpr.so")
+
+QPR_OK, QPR_E_ARG, QPR_E_HIP, QPR_E_NOT_CONVERGED = 0, -1, -2, -3
+QPR_E_NONFINITE, QPR_E_UNSTABLE, QPR_E_WORKSPACE = -4, -5, -6
+STATUS_NAMES = {0: "QPR_OK", -1: "QPR_E_ARG", -2: "QPR_E_HIP", -3: "QPR_E_NOT_CONVERGED",
+                -4: "QPR_E_NONFINITE", -5: "QPR_E_UNSTABLE", -6: "QPR_E_WORKSPACE"}
+TELEPORT = {"paper_f": 0, "uniform": 1}
+HDIAG = {"zero": 0, "paper": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# every symbol include/qpr.h declares
+EXPORTS = (
+    "qpr_problem_bytes", "qpr_build_google", "qpr_workspace_bytes", "qpr_rhs",
+    "qpr_rk4_step", "qpr_steady_state", "qpr_rank", "qpr_last_error", "qpr_version",
+    "qpr_time_kernels", "qpr_product_configs", "qpr_product_config_name",
+    "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
+    "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam",
+)
+
+
+class QprError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class qpr_problem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("ld", C.c_int32), ("n_edges_in", C.c_int64), ("nnz_a", C.c_int64),
+        ("nnz_h", C.c_int64), ("n_self_loops", C.c_int32), ("n_dangling", C.c_int32),
+        ("alpha", C.c_double), ("teleport", C.c_int32), ("hdiag", C.c_int32),
+        ("h_lo", C.c_double), ("h_hi", C.c_double), ("pagerank_iters", C.c_int32),
+        ("reserved", C.c_int32),
+        ("h_off", C.c_void_p), ("h_off_f32", C.c_void_p), ("h_off_bf16", C.c_void_p),
+        ("h_diag", C.c_void_p), ("d", C.c_void_p), ("inv_outdeg", C.c_void_p),
+        ("dangling", C.c_void_p), ("outdeg", C.c_void_p), ("indeg", C.c_void_p),
+        ("in_ptr", C.c_void_p), ("in_idx", C.c_void_p), ("out_ptr", C.c_void_p),
+        ("out_idx", C.c_void_p), ("pagerank", C.c_void_p), ("arena", C.c_void_p),
+        ("arena_bytes", C.c_size_t),
+    ]
+
+
+class qpr_stats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("rhs_evals", C.c_int64), ("rhs_evals_fp64", C.c_int64),
+        ("folds", C.c_int64), ("t", C.c_double), ("residual", C.c_double),
+        ("trace_err", C.c_double), ("herm_err", C.c_double), ("min_diag", C.c_double),
+        ("seconds", C.c_double), ("converged", C.c_int32), ("status", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class qpr_mpnn_batch(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_graphs", C.c_int32), ("x", C.c_void_p),
+                ("in_ptr", C.c_void_p), ("in_idx", C.c_void_p), ("out_ptr", C.c_void_p),
+                ("out_idx", C.c_void_p), ("inv_in", C.c_void_p), ("inv_out", C.c_void_p),
+                ("graph_ptr", C.c_void_p)]
+
+
+class qpr_opts(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("use_graph", C.c_int32), ("fold_every", C.c_int32),
+                ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqpr.so (raises QprError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QprError(QPR_E_HIP, f"{LIB_PATH} is missing; build it with "
+                                  "`python -m paper_2003_04930_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    P = C.POINTER(qpr_problem)
+    sig = {
+        "qpr_problem_bytes": (sz, [i32, i64]),
+        "qpr_build_google": (i32, [i32, i64, vp, vp, dbl, i32, i32, vp, sz, P, vp]),
+        "qpr_workspace_bytes": (sz, [i32, i32]),
+        "qpr_rhs": (i32, [P, dbl, vp, vp, i32, vp, sz, vp]),
+        "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, vp, sz, vp]),
+        "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
+                                   C.POINTER(qpr_opts), vp, sz, vp]),
+        "qpr_rank": (i32, [i32, vp, vp, vp]),
+        "qpr_time_kernels": (i32, [P, dbl, i32, i32, i32, vp, C.POINTER(C.c_double), vp, sz, vp]),
+        "qpr_product_configs": (i32, [i32]),
+        "qpr_product_config_name": (C.c_char_p, [i32, i32]),
+        "qpr_mpnn_param_count": (i32, []),
+        "qpr_mpnn_workspace_bytes": (sz, [i32, i32]),
+        "qpr_mpnn_features": (i32, [P, dbl, vp, vp, vp, vp]),
+        "qpr_mpnn_forward": (i32, [C.POINTER(qpr_mpnn_batch), vp, vp, vp, sz, vp]),
+        "qpr_mpnn_backward": (i32, [C.POINTER(qpr_mpnn_batch), vp, vp, vp, vp, vp, sz, vp]),
+        "qpr_mpnn_adam": (i32, [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float,
+                                C.c_float, vp]),
+        "qpr_last_error": (C.c_char_p, []),
+        "qpr_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != QPR_OK and status not in allow:
+        raise QprError(status, lib().qpr_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def version() -> str:
+    return lib().qpr_version().decode()
+
+
+# ------------------------------------------------------------------ problem
+class Problem:
+    """A built problem (qpr_build_google) owning its device arena."""
+
+    def __init__(self, n, src, dst, alpha=0.85, teleport="paper_f", hdiag="zero", device="cuda"):
+        torch = _torch()
+        L = lib()
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst must have the same length")
+        nbytes = L.qpr_problem_bytes(int(n), int(src.size))
+        if nbytes == 0:
+            raise QprError(QPR_E_ARG, f"invalid problem size n={n}, E={src.size}")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.arena.data_ptr()) % 256
+        self._base = self.arena.data_ptr() + off
+        self.p = qpr_problem()
+        _check(L.qpr_build_google(int(n), int(src.size), src.ctypes.data_as(C.c_void_p),
+                                  dst.ctypes.data_as(C.c_void_p), float(alpha),
+                                  TELEPORT[teleport], HDIAG[hdiag], C.c_void_p(self._base),
+                                  nbytes, C.byref(self.p), _stream()))
+        self.alpha, self.teleport, self.hdiag = alpha, teleport, hdiag
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        return cls(g.n, g.src, g.dst, **kw)
+
+    @property
+    def n(self):
+        return self.p.n
+
+    @property
+    def ld(self):
+        return self.p.ld
+
+    def _view(self, ptr, count, dtype):
+        torch = _torch()
+        item = torch.empty((), dtype=dtype).element_size()
+        off = ptr - self.arena.data_ptr()
+        return self.arena[off:off + count * item].view(dtype)
+
+    def h_off(self):
+        torch = _torch()
+        return self._view(self.p.h_off, self.ld * self.ld, torch.float64).view(self.ld, self.ld)
+
+    def vector(self, name):
+        torch = _torch()
+        if name in ("h_diag", "d", "inv_outdeg", "pagerank"):
+            return self._view(getattr(self.p, name), self.n, torch.float64)
+        if name in ("dangling", "outdeg", "indeg"):
+            return self._view(getattr(self.p, name), self.n, torch.int32)
+        if name in ("in_ptr", "out_ptr"):
+            return self._view(getattr(self.p, name), self.n + 1, torch.int32)
+        if name in ("in_idx", "out_idx"):
+            return self._view(getattr(self.p, name), self.p.nnz_a, torch.int32)
+        raise KeyError(name)
+
+
+class Workspace:
+    """Device workspace for one problem size and precision."""
+
+    def __init__(self, n, prec="fp64", device="cuda"):
+        torch = _torch()
+        nbytes = lib().qpr_workspace_bytes(int(n), PREC[prec])
+        if nbytes == 0:
+            raise QprError(QPR_E_ARG, f"invalid workspace request n={n} prec={prec}")
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self.ptr = self.buf.data_ptr() + (-self.buf.data_ptr()) % 256
+        self.nbytes = nbytes
+        self.n, self.prec = n, prec
+
+
+_ws_cache = {}
+
+
+def workspace(n, prec="fp64"):
+    key = (int(n), prec)
+    ws = _ws_cache.get(key)
+    if ws is None:
+        ws = _ws_cache[key] = Workspace(n, prec)
+    return ws
+
+
+# ----------------------------------------------------------- conversions
+def planar(rho, device="cuda"):
+    """complex numpy/torch (n,n) -> planar float64 (2,n,n) device tensor."""
+    torch = _torch()
+    if isinstance(rho, np.ndarray):
+        rho = torch.from_numpy(np.ascontiguousarray(rho, dtype=np.complex128))
+    if rho.is_complex():
+        out = torch.stack([rho.real, rho.imag]).to(torch.float64)
+    else:
+        out = rho.to(torch.float64)
+    return out.to(device).contiguous()
+
+
+def to_complex(rho_planar) -> np.ndarray:
+    r = rho_planar.detach().cpu().numpy()
+    return r[0] + 1j * r[1]
+
+
+def _planar_arg(rho, n):
+    torch = _torch()
+    if not (isinstance(rho, torch.Tensor) and rho.dtype == torch.float64 and rho.is_cuda
+            and rho.is_contiguous() and tuple(rho.shape) == (2, n, n)):
+        raise ValueError(f"rho must be a contiguous float64 CUDA tensor of shape (2,{n},{n})")
+    return rho
+
+
+# --------------------------------------------------------------- entry points
+def rhs(P: Problem, omega, rho, prec="fp64", out=None):
+    torch = _torch()
+    rho = _planar_arg(rho, P.n)
+    if out is None:
+        out = torch.empty_like(rho)
+    ws = workspace(P.n, prec)
+    _check(lib().qpr_rhs(C.byref(P.p), float(omega), _ptr(rho), _ptr(out), PREC[prec],
+                         C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+    return out
+
+
+def rk4_step(P: Problem, omega, dt, nsteps, rho, prec="fp64", diag=False):
+    """nsteps RK4 steps in place; returns [res^2, trace, herm, nonfinite] if diag."""
+    torch = _torch()
+    rho = _planar_arg(rho, P.n)
+    ws = workspace(P.n, prec)
+    d = torch.zeros(4, dtype=torch.float64, device=rho.device) if diag else None
+    _check(lib().qpr_rk4_step(C.byref(P.p), float(omega), float(dt), int(nsteps), _ptr(rho),
+                              PREC[prec], _ptr(d), C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+    return d
+
+
+@dataclass
+class SolveResult:
+    rho: "object"
+    rank: "object"
+    stats: dict
+    status: int
+
+
+def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0=None,
+                 want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1,
+                 allow_not_converged=False):
+    torch = _torch()
+    n = P.n
+    if rho0 is None:
+        rho = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+        rho[0].diagonal().fill_(1.0 / n)
+    else:
+        rho = _planar_arg(rho0, n).clone()
+    rank = torch.empty(n, dtype=torch.int32, device="cuda") if want_rank else None
+    st = qpr_stats()
+    op = qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm), int(gemm_cfg))
+    ws = workspace(n, prec)
+    status = lib().qpr_steady_state(C.byref(P.p), float(omega), float(dt), float(tol),
+                                    int(max_steps), PREC[prec], _ptr(rho), _ptr(rank),
+                                    C.byref(st), C.byref(op), C.c_void_p(ws.ptr), ws.nbytes,
+                                    _stream())
+    _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
+    return SolveResult(rho, rank, st.as_dict(), status)
+
+
+def rank(p):
+    """Order of nodes by descending p (ties: ascending index), on the GPU."""
+    torch = _torch()
+    p = p.to(torch.float64).contiguous()
+    order = torch.empty(p.numel(), dtype=torch.int32, device=p.device)
+    _check(lib().qpr_rank(int(p.numel()), _ptr(p), _ptr(order), _stream()))
+    return order
+
+
+def time_kernels(P: Problem, omega, rho, prec="fp64", cfg=-1, reps=50):
+    """Mean ms per launch of (product, stage-1 epilogue), timed with HIP events."""
+    rho = _planar_arg(rho, P.n)
+    ws = workspace(P.n, prec)
+    out = (C.c_double * 2)()
+    _check(lib().qpr_time_kernels(C.byref(P.p), float(omega), PREC[prec], int(cfg), int(reps),
+                                  _ptr(rho), out, C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+    return float(out[0]), float(out[1])
+
+
+def product_configs(prec="fp64"):
+    L = lib()
+    return [L.qpr_product_config_name(PREC[prec], i).decode()
+            for i in range(L.qpr_product_configs(PREC[prec]))]
+
+
+# ------------------------------------------------------- learned warm start
+def mpnn_param_count() -> int:
+    return int(lib().qpr_mpnn_param_count())
+
+
+class MpnnBatch:
+    """Block-diagonal batch of (problem, omega) pairs for the warm-start network.
+
+    Features come from qpr_mpnn_features on each built problem; the CSR
+    arrays are the problems' own in/out link lists shifted by node offsets.
+    """
+
+    def __init__(self, items):
+        torch = _torch()
+        xs, ii, oo, ip, ix, op, ox, offs = [], [], [], [], [], [], [], [0]
+        base = nnz_in = nnz_out = 0
+        for P, omega in items:
+            n = P.n
+            x = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+            inv_in = torch.empty(n, dtype=torch.float32, device="cuda")
+            inv_out = torch.empty(n, dtype=torch.float32, device="cuda")
+            _check(lib().qpr_mpnn_features(C.byref(P.p), float(omega), _ptr(x), _ptr(inv_in),
+                                           _ptr(inv_out), _stream()))
+            xs.append(x)
+            ii.append(inv_in)
+            oo.append(inv_out)
+            ip.append(P.vector("in_ptr")[:-1].to(torch.int64) + nnz_in)
+            ix.append(P.vector("in_idx").to(torch.int64) + base)
+            op.append(P.vector("out_ptr")[:-1].to(torch.int64) + nnz_out)
+            ox.append(P.vector("out_idx").to(torch.int64) + base)
+            nnz_in += int(P.p.nnz_a)
+            nnz_out += int(P.p.nnz_a)
+            base += n
+            offs.append(base)
+        nnz = sum(int(t.numel()) for t in ix)
+        i32 = torch.int32
+        self.x = torch.cat(xs).contiguous()
+        self.inv_in = torch.cat(ii).contiguous()
+        self.inv_out = torch.cat(oo).contiguous()
+        self.in_ptr = torch.cat(ip + [torch.tensor([nnz], device="cuda")]).to(i32).contiguous()
+        self.in_idx = torch.cat(ix).to(i32).contiguous() if nnz else torch.zeros(1, dtype=i32, device="cuda")
+        self.out_ptr = torch.cat(op + [torch.tensor([nnz], device="cuda")]).to(i32).contiguous()
+        self.out_idx = torch.cat(ox).to(i32).contiguous() if nnz else torch.zeros(1, dtype=i32, device="cuda")
+        self.graph_ptr = torch.tensor(offs, dtype=i32, device="cuda")
+        self.n_nodes, self.n_graphs = base, len(items)
+        self.c = qpr_mpnn_batch(self.n_nodes, self.n_graphs, self.x.data_ptr(),
+                                self.in_ptr.data_ptr(), self.in_idx.data_ptr(),
+                                self.out_ptr.data_ptr(), self.out_idx.data_ptr(),
+                                self.inv_in.data_ptr(), self.inv_out.data_ptr(),
+                                self.graph_ptr.data_ptr())
+        nbytes = lib().qpr_mpnn_workspace_bytes(self.n_nodes, self.n_graphs)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.ws_ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self.ws_bytes = nbytes
+
+
+def mpnn_forward(batch: MpnnBatch, params):
+    torch = _torch()
+    p_hat = torch.empty(batch.n_nodes, dtype=torch.float32, device="cuda")
+    _check(lib().qpr_mpnn_forward(C.byref(batch.c), _ptr(params), _ptr(p_hat),
+                                  C.c_void_p(batch.ws_ptr), batch.ws_bytes, _stream()))
+    return p_hat
+
+
+def mpnn_backward(batch: MpnnBatch, params, p_true):
+    """Gradient and loss after mpnn_forward on the same batch."""
+    torch = _torch()
+    grads = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().qpr_mpnn_backward(C.byref(batch.c), _ptr(params), _ptr(p_true), _ptr(grads),
+                                   _ptr(loss), C.c_void_p(batch.ws_ptr), batch.ws_bytes,
+                                   _stream()))
+    return grads, loss
+
+
+def mpnn_adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(lib().qpr_mpnn_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(params.numel()),
+                               int(step), float(lr), float(b1), float(b2), float(eps), _stream()))

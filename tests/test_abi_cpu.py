@@ -1,0 +1,125 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, the ctypes structs match the C layout, and argument checks
+that precede any device work return the documented status codes."""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2003_04930_amd import qpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qpr.h")
+
+
+def _lib():
+    if not os.path.exists(qpr.LIB_PATH):
+        pytest.fail("libqpr.so is not built (run __graft_entry__.build())")
+    return qpr.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qpr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib()
+    names = declared_functions()
+    assert "qpr_steady_state" in names and len(names) >= 9
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(qpr.EXPORTS)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "lay.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "qpr.h"
+int main(void){
+  printf("%zu %zu %zu\n", sizeof(qpr_problem), sizeof(qpr_stats), sizeof(qpr_opts));
+  printf("%zu %zu %zu\n", offsetof(qpr_problem, h_off), offsetof(qpr_problem, pagerank), offsetof(qpr_problem, arena_bytes));
+  printf("%zu %zu\n", offsetof(qpr_stats, seconds), offsetof(qpr_stats, status));
+  return 0;
+}''')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [C.sizeof(qpr.qpr_problem), C.sizeof(qpr.qpr_stats), C.sizeof(qpr.qpr_opts),
+            qpr.qpr_problem.h_off.offset, qpr.qpr_problem.pagerank.offset,
+            qpr.qpr_problem.arena_bytes.offset, qpr.qpr_stats.seconds.offset,
+            qpr.qpr_stats.status.offset]
+    assert got == want
+
+
+def test_size_queries_and_version():
+    L = _lib()
+    assert L.qpr_problem_bytes(1, 0) == 0
+    b922 = L.qpr_problem_bytes(922, 3031)
+    assert b922 > 960 * 960 * (8 + 4 + 2)
+    assert L.qpr_workspace_bytes(1, 0) == 0
+    assert L.qpr_workspace_bytes(922, 7) == 0
+    w64 = L.qpr_workspace_bytes(922, 0)
+    assert w64 >= 10 * 960 * 960 * 8
+    assert L.qpr_workspace_bytes(922, 2) > w64
+    assert b"gfx950" in L.qpr_version()
+
+
+def _build(n, src, dst, alpha=0.85, teleport=0, hdiag=0, arena=C.c_void_p(256), nbytes=1 << 40):
+    L = _lib()
+    src = np.asarray(src, dtype=np.int32)
+    dst = np.asarray(dst, dtype=np.int32)
+    P = qpr.qpr_problem()
+    return L.qpr_build_google(n, src.size, src.ctypes.data_as(C.c_void_p),
+                              dst.ctypes.data_as(C.c_void_p), alpha, teleport, hdiag, arena,
+                              nbytes, C.byref(P), None)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(n=1, src=[], dst=[]), "n must be"),
+    (dict(n=4, src=[0], dst=[1], alpha=1.5), "alpha"),
+    (dict(n=4, src=[0], dst=[1], teleport=7), "teleport"),
+    (dict(n=4, src=[0], dst=[1], hdiag=3), "hdiag"),
+    (dict(n=4, src=[0, 5], dst=[1, 2]), "out of range"),
+    (dict(n=4, src=[0], dst=[-1]), "out of range"),
+    (dict(n=4, src=[0], dst=[1], arena=C.c_void_p(0)), "NULL"),
+    (dict(n=4, src=[0], dst=[1], arena=C.c_void_p(8)), "aligned"),
+])
+def test_build_argument_errors(kw, needle):
+    assert _build(**kw) == qpr.QPR_E_ARG
+    assert needle in _lib().qpr_last_error().decode()
+
+
+def test_build_arena_too_small():
+    assert _build(4, [0], [1], nbytes=16) == qpr.QPR_E_WORKSPACE
+
+
+def test_solver_argument_errors_before_device_work():
+    L = _lib()
+    st = qpr.qpr_stats()
+    assert L.qpr_rhs(None, 0.5, None, None, 0, None, 0, None) == qpr.QPR_E_ARG
+    assert L.qpr_steady_state(None, 0.5, 0.01, 1e-8, 10, 0, None, None, C.byref(st), None, None,
+                              0, None) == qpr.QPR_E_ARG
+    assert L.qpr_rank(0, None, None, None) == qpr.QPR_E_ARG
+    # a fake problem with bad ld is rejected before any HIP call
+    P = qpr.qpr_problem()
+    P.n, P.ld = 10, 10
+    assert L.qpr_rk4_step(C.byref(P), 0.5, 0.01, 1, C.c_void_p(256), 0, None, C.c_void_p(256),
+                          1 << 30, None) == qpr.QPR_E_ARG
+    assert "built problem" in L.qpr_last_error().decode()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(qpr, "_lib", None)
+    monkeypatch.setattr(qpr, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(qpr.QprError):
+        qpr.lib()

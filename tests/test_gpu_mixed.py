@@ -1,0 +1,98 @@
+"""Mixed-precision products (FP32, BF16x3) and the FP64-judged defect
+correction, against the CPU FP64 oracle.
+
+Bounds: a low-precision product row sums at most deg(a) terms of the FP32
+(or 3-slice bf16, 24-bit) representation of rho with FP32 accumulation, so
+|X_lowp - X| <= c * 2^-24 * deg_max * max|rho|; the right-hand side inherits
+that times (1 - omega).  The steady state is judged by the FP64 residual, so
+the mixed solution must satisfy ||L(rho)||_F < tol re-measured by the oracle
+and lie within 1e-6 of the oracle's steady state (the benchmark spec's bound).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_04930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2003_04930_amd import qpr
+    qpr.lib()
+    assert torch.cuda.is_available()
+    return qpr
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,m,omega", [(70, 2, 0.3), (130, 3, 0.8), (922, 3, 0.5)])
+def test_lowp_rhs_error_bound(Q, prec, n, m, omega):
+    g = inputs.ba_digraph(n, m, seed=n)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    rho = inputs.random_density(n, seed=3)
+    got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho), prec=prec))
+    want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, omega)
+    deg = int((R.H != 0).sum(axis=1).max())
+    bound = 8 * 2.0 ** -24 * (deg + 1) * np.max(np.abs(rho)) * (1 - omega) + 1e-15
+    err = np.max(np.abs(got - want))
+    assert err <= bound, (err, bound)
+    assert err > 0 or omega == 1.0          # it really is the low-precision path
+    assert np.array_equal(got, got.conj().T)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_steady_state_matches_oracle(Q, prec):
+    g = inputs.ba_digraph(130, 3, seed=1)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    omega, dt, tol = 0.6, 0.01, 1e-9
+    f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
+    want, nsteps, _ = O.steady_ref(np.eye(g.n) / g.n, f, dt, tol, 200000)
+    out = Q.steady_state(P, omega, dt, tol, 200000, prec=prec, chunk=32, fold_every=32)
+    got = Q.to_complex(out.rho)
+    assert out.stats["converged"] == 1
+    assert out.stats["folds"] >= 2
+    assert np.sqrt(np.sum(np.abs(f(got)) ** 2)) < tol * (1 + 1e-6)
+    assert np.max(np.abs(got - want)) < 1e-6
+    assert abs(np.trace(got).real - 1) < 1e-12
+    assert out.stats["herm_err"] == 0.0
+    # step count within one fold period of the plain FP64 integration
+    assert abs(out.stats["steps"] - nsteps) <= 32 + 5
+    p_want = np.diag(want).real
+    tau = 2 * np.max(np.abs(got - want)) + 1e-15
+    order = out.rank.cpu().numpy()
+    pos = np.empty_like(order)
+    pos[order] = np.arange(g.n)
+    for i in range(g.n):
+        for j in range(g.n):
+            if p_want[i] > p_want[j] + tau:
+                assert pos[i] < pos[j]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_n922_against_fp64_gpu(Q, prec):
+    g = inputs.ba_digraph(922, 3, seed=0)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    ref = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000)
+    out = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000, prec=prec)
+    a, b = Q.to_complex(out.rho), Q.to_complex(ref.rho)
+    assert np.max(np.abs(a - b)) < 1e-6
+    res = np.sqrt(np.sum(np.abs(O.rhs_ref(a, R.H_sparse, R.G, R.d, 0.8)) ** 2))
+    assert res < 1e-8 * (1 + 1e-6)
+
+
+def test_lowp_rk4_trajectory_close_to_fp64(Q):
+    g = inputs.ba_digraph(200, 3, seed=4)
+    P = Q.Problem.from_graph(g)
+    rho0 = inputs.random_density(200, seed=9)
+    x64 = Q.planar(rho0)
+    Q.rk4_step(P, 0.5, 0.01, 30, x64)
+    for prec in ("fp32", "bf16x3"):
+        x = Q.planar(rho0)
+        Q.rk4_step(P, 0.5, 0.01, 30, x, prec=prec)
+        err = (x - x64).abs().max().item()
+        assert 0 < err < 1e-7

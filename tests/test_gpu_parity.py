@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (FP64 throughout): the right-hand side and stage updates differ
+from the oracle only in summation order, |dL| <= ~deg * eps * max|rho|, so
+1e-12 absolute on trace-one states; step-locked trajectories stay within
+1e-10 (the benchmark spec's bound for plain FP64; observed ~1e-14); integer and
+index outputs (CSR, degrees, ranking) are compared exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_04930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2003_04930_amd import qpr
+    qpr.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return qpr
+
+
+def oracle_problem(g, **kw):
+    return O.problem_ref(g.n, g.src, g.dst, **kw)
+
+
+GRAPHS = {
+    "er16": lambda: inputs.er_digraph(16, 0.2, seed=0),
+    "er70": lambda: inputs.er_digraph(70, 0.06, seed=3),         # ragged: 70 -> ld 128
+    "ba130": lambda: inputs.ba_digraph(130, 3, seed=1),           # several tiles + tail
+    "ba300": lambda: inputs.ba_digraph(300, 2, seed=2),
+}
+
+
+# ------------------------------------------------------------------- build
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+@pytest.mark.parametrize("teleport,hdiag", [("paper_f", "zero"), ("uniform", "paper")])
+def test_build_matches_oracle(Q, name, teleport, hdiag):
+    g = GRAPHS[name]()
+    # add a self-loop and a duplicate to exercise the cleaning rules
+    src = np.concatenate([g.src, [0, g.src[0]]]).astype(np.int32)
+    dst = np.concatenate([g.dst, [0, g.dst[0]]]).astype(np.int32)
+    P = Q.Problem(g.n, src, dst, teleport=teleport, hdiag=hdiag)
+    R = O.problem_ref(g.n, src, dst, teleport=teleport, hdiag=hdiag)
+    n = g.n
+    H = P.h_off().cpu().numpy()
+    offdiag = R.H - np.diag(np.diag(R.H))
+    assert np.array_equal(H[:n, :n], offdiag)
+    assert np.all(H[n:, :] == 0) and np.all(H[:, n:] == 0)
+    assert np.array_equal(P.vector("h_diag").cpu().numpy(), np.diag(R.H))
+    # the oracle sums each column of G in float64: its own error is ~n eps
+    assert np.max(np.abs(P.vector("d").cpu().numpy() - R.d)) < 2 * n * np.finfo(float).eps
+    assert np.array_equal(P.vector("outdeg").cpu().numpy(), O.out_degree(R.A).astype(np.int32))
+    assert np.array_equal(P.vector("indeg").cpu().numpy(), R.A.sum(axis=1).astype(np.int32))
+    assert np.array_equal(P.vector("dangling").cpu().numpy(), (O.out_degree(R.A) == 0).astype(np.int32))
+    ptr = P.vector("in_ptr").cpu().numpy()
+    idx = P.vector("in_idx").cpu().numpy()
+    for a in range(n):
+        assert list(idx[ptr[a]:ptr[a + 1]]) == list(np.nonzero(R.A[a])[0])
+    assert P.p.n_self_loops == 1
+    assert P.p.nnz_a == int(R.A.sum())
+    assert P.p.nnz_h == int(np.count_nonzero(offdiag))
+    pr = P.vector("pagerank").cpu().numpy()
+    assert np.max(np.abs(pr - O.pagerank_power(R.G))) < 1e-13
+    lam = np.linalg.eigvalsh(R.H)
+    assert P.p.h_lo <= lam[0] + 1e-12 and lam[-1] <= P.p.h_hi + 1e-12
+
+
+# --------------------------------------------------------------------- rhs
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+@pytest.mark.parametrize("omega", [0.0, 0.35, 0.8, 1.0])
+def test_rhs_fp64_matches_oracle(Q, name, omega):
+    g = GRAPHS[name]()
+    for teleport, hdiag in (("paper_f", "zero"), ("uniform", "paper")):
+        P = Q.Problem.from_graph(g, teleport=teleport, hdiag=hdiag)
+        R = oracle_problem(g, teleport=teleport, hdiag=hdiag)
+        rho = inputs.random_density(g.n, seed=g.n)
+        got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho)))
+        want = O.rhs_ref(rho, R.H, R.G, R.d, omega)
+        assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+        assert np.array_equal(got, got.conj().T)          # bitwise Hermitian
+
+
+# -------------------------------------------------------------- RK4 steps
+@pytest.mark.parametrize("name,steps", [("er16", 60), ("er70", 25), ("ba130", 12)])
+def test_rk4_steps_step_locked(Q, name, steps):
+    g = GRAPHS[name]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    omega, dt = 0.8, 0.01
+    rho0 = inputs.random_density(g.n, seed=5)
+    x = Q.planar(rho0)
+    d = Q.rk4_step(P, omega, dt, steps, x, diag=True)
+    got = Q.to_complex(x)
+    want = O.rk4_ref(rho0, lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega), dt, steps)
+    assert np.max(np.abs(got - want)) < 1e-12
+    dd = d.cpu().numpy()
+    assert abs(dd[1] - np.trace(want).real) < 1e-12
+    assert dd[2] == 0.0 and dd[3] == 0.0
+
+
+# ---------------------------------------------------------- steady state
+def test_steady_state_config1_matches_oracle(Q):
+    g = GRAPHS["er16"]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    omega, dt, tol = 0.8, 0.01, 1e-10
+    f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
+    want, nsteps, res = O.steady_ref(np.eye(16) / 16, f, dt, tol, 100000)
+    out = Q.steady_state(P, omega, dt, tol, 100000)
+    got = Q.to_complex(out.rho)
+    assert out.stats["steps"] == nsteps
+    assert out.stats["converged"] == 1
+    assert np.max(np.abs(got - want)) < 1e-10
+    assert abs(out.stats["residual"] - res) < 1e-13
+    assert out.stats["herm_err"] == 0.0
+    assert list(out.rank.cpu().numpy()) == list(O.rank_ref(np.diag(want).real))
+
+
+@pytest.mark.parametrize("chunk,use_graph", [(7, False), (64, True), (5, True)])
+def test_steady_state_graph_and_chunking_do_not_change_result(Q, chunk, use_graph):
+    g = GRAPHS["er70"]()
+    P = Q.Problem.from_graph(g)
+    ref = Q.steady_state(P, 0.5, 0.01, 1e-9, 100000, chunk=64, use_graph=False)
+    out = Q.steady_state(P, 0.5, 0.01, 1e-9, 100000, chunk=chunk, use_graph=use_graph)
+    assert out.stats["steps"] == ref.stats["steps"]
+    assert torch.equal(out.rho, ref.rho)
+
+
+def test_steady_state_ba130_properties_and_oracle(Q):
+    g = GRAPHS["ba130"]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    omega, dt, tol = 0.6, 0.01, 1e-9
+    f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
+    want, nsteps, _ = O.steady_ref(np.eye(g.n) / g.n, f, dt, tol, 100000)
+    out = Q.steady_state(P, omega, dt, tol, 100000)
+    got = Q.to_complex(out.rho)
+    assert out.stats["steps"] == nsteps
+    assert np.max(np.abs(got - want)) < 1e-10
+    assert np.sqrt(np.sum(np.abs(f(got)) ** 2)) < tol
+    assert np.min(np.linalg.eigvalsh(got)) > -1e-12
+
+
+def test_not_converged_returns_last_state(Q):
+    g = GRAPHS["er16"]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    out = Q.steady_state(P, 0.8, 0.01, 1e-14, 37, allow_not_converged=True)
+    assert out.status == Q.QPR_E_NOT_CONVERGED
+    assert out.stats["steps"] == 37
+    want = O.rk4_ref(np.eye(16) / 16, lambda r: O.rhs_ref(r, R.H, R.G, R.d, 0.8), 0.01, 37)
+    assert np.max(np.abs(Q.to_complex(out.rho) - want)) < 1e-13
+
+
+def test_error_paths(Q):
+    g = GRAPHS["er16"]()
+    P = Q.Problem.from_graph(g)
+    rho = Q.planar(np.eye(16) / 16)
+    with pytest.raises(Q.QprError) as e:
+        Q.rhs(P, 1.5, rho)
+    assert e.value.status == Q.QPR_E_ARG and "omega" in e.value.message
+    with pytest.raises(Q.QprError) as e:
+        Q.rk4_step(P, 0.1, 5.0, 1, rho)
+    assert e.value.status == Q.QPR_E_UNSTABLE
+    bad = rho.clone()
+    bad[0, 3, 3] = float("nan")
+    with pytest.raises(Q.QprError) as e:
+        Q.steady_state(P, 0.8, 0.01, 1e-10, 1000, rho0=bad)
+    assert e.value.status == Q.QPR_E_NONFINITE
+    with pytest.raises(Q.QprError) as e:
+        Q.Problem(4, [0, 1], [1, 9])
+    assert e.value.status == Q.QPR_E_ARG
+
+
+# ---------------------------------------------------------------- ranking
+def test_rank_kernel_with_ties(Q):
+    rng = np.random.default_rng(0)
+    for n in (1, 7, 256, 1000, 4099):
+        p = rng.integers(0, max(2, n // 5), size=n).astype(np.float64) / 7.0  # many ties
+        got = Q.rank(torch.from_numpy(p).cuda()).cpu().numpy()
+        assert list(got) == list(O.rank_ref(p))
+
+
+# --------------------------------------------------------- full-size cases
+@pytest.mark.parametrize("n,m", [(922, 3), (4096, 4)])
+def test_rhs_full_size(Q, n, m):
+    g = inputs.ba_digraph(n, m, seed=0)
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    rho = inputs.random_density(n, seed=1)
+    got = Q.to_complex(Q.rhs(P, 0.8, Q.planar(rho)))
+    want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.8)
+    assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_steady_state_n922_properties(Q):
+    """Config-2 graph at omega = 0.8 to 1e-8: residual re-measured by the
+    oracle, trace, Hermiticity, positivity, and a step-locked prefix."""
+    g = inputs.ba_digraph(922, 3, seed=0)
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    out = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000)
+    rho = Q.to_complex(out.rho)
+    res = np.sqrt(np.sum(np.abs(O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.8)) ** 2))
+    assert res < 1e-8 * (1 + 1e-6)
+    assert abs(np.trace(rho).real - 1) < 1e-11
+    assert np.array_equal(rho, rho.conj().T)
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-12
+    x = Q.planar(np.eye(922) / 922)
+    Q.rk4_step(P, 0.8, 0.01, 8, x)
+    want = O.rk4_ref(np.eye(922) / 922, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, 0.8), 0.01, 8)
+    assert np.max(np.abs(Q.to_complex(x) - want)) < 1e-12
