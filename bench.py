@@ -39,10 +39,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def solve_all(Q, P, prec, rho0_fn=None):
+def solve_all(Q, P, prec, rho0_fn=None, product="auto"):
     out = []
     for w in OMEGAS:
-        r = Q.steady_state(P, w, DT, TOL, 400000, prec=prec,
+        r = Q.steady_state(P, w, DT, TOL, 400000, prec=prec, product=product,
                            rho0=None if rho0_fn is None else rho0_fn(w))
         out.append(r)
     return out
@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -118,23 +119,53 @@ def main():
     value = ms_per_step / 1e3 / len(OMEGAS)
     log(f"fp64: {value:.3f} s/solve, steps {steps}")
 
-    # dominant kernel: the FP64 commutator product, timed on the same stream
+    # Kernels of the timed path, timed with HIP events on the solve's stream.
+    # The auto product at this density is the sparse fused stage (one launch
+    # per stage); the dense MFMA product and its epilogue are timed too.
     rho_ss = results[-1].rho
+    sparse = P.p.nnz_h < 0.05 * N * N
+    _, sp_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", cfg=-2, reps=200)
     gemm_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
     ld = P.ld
-    flops = 4.0 * N ** 3                       # algorithmic: two real N x N x N products
-    achieved = flops / (gemm_ms * 1e-3) / 1e12
-    epi_bytes = 16.0 * N * N * 9               # stage-1 pass: 5 complex reads + 4 writes
-    epi_gbs = epi_bytes / (epi_ms * 1e-3) / 1e9
-    log(f"product {gemm_ms * 1e3:.1f} us ({achieved:.1f} TF/s), epilogue {epi_ms * 1e3:.1f} us "
-        f"({epi_gbs:.0f} GB/s)")
+    stage_bytes = 16.0 * N * N * 5             # interior stage: read Y_s, y_n, acc; write acc, Y_s+1
+    flops = 4.0 * N ** 3                       # dense product: two real N x N x N products
+    gemm_tf = flops / (gemm_ms * 1e-3) / 1e12
+    epi_gbs = (stage_bytes + 32.0 * N * N) / (epi_ms * 1e-3) / 1e9   # + X_ab, X_ba reads
+    sp_gbs = stage_bytes / (sp_ms * 1e-3) / 1e9
+    log(f"sparse stage {sp_ms * 1e3:.1f} us ({sp_gbs:.0f} GB/s algorithmic); dense product "
+        f"{gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s), dense epilogue {epi_ms * 1e3:.1f} us")
+    if sparse:
+        roofline = {"bound": "hbm", "achieved": sp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": sp_gbs / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_epilogue<XS_SPARSE64> (fused sparse RK4 stage)",
+                    "bytes_per_launch": stage_bytes, "us_per_launch": sp_ms * 1e3}
+    else:
+        roofline = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": gemm_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                    "kernel": "k_gemm_k4<double> (dense commutator product)",
+                    "flops_per_launch": flops, "us_per_launch": gemm_ms * 1e3}
 
     extra = {"per_omega_fp64": per_omega, "build_seconds": t_build,
-             "solves_per_s_fp64": 1.0 / value,
-             "epilogue": {"achieved_GBs": epi_gbs, "peak_GBs": HBM_PEAK_GBS,
-                          "frac": epi_gbs / HBM_PEAK_GBS, "us": epi_ms * 1e3,
-                          "bytes_per_launch": epi_bytes},
-             "product_us": gemm_ms * 1e3, "ld": ld}
+             "solves_per_s_fp64": 1.0 / value, "product": "sparse" if sparse else "dense",
+             "dense_product": {"us": gemm_ms * 1e3, "achieved_TFs": gemm_tf,
+                               "peak_TFs": FP64_PEAK_TFLOPS, "frac": gemm_tf / FP64_PEAK_TFLOPS,
+                               "flops_per_launch": flops},
+             "dense_epilogue": {"us": epi_ms * 1e3, "achieved_GBs": epi_gbs,
+                                "frac": epi_gbs / HBM_PEAK_GBS},
+             "sparse_stage": {"us": sp_ms * 1e3, "achieved_GBs": sp_gbs,
+                              "frac": sp_gbs / HBM_PEAK_GBS},
+             "nnz_h": int(P.p.nnz_h), "ld": ld}
+
+    if not args.no_dense:
+        t0d = time.perf_counter()
+        rd = solve_all(Q, P, "fp64", product="dense")
+        torch.cuda.synchronize()
+        td = (time.perf_counter() - t0d) / len(OMEGAS)
+        err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rd, results))
+        extra["fp64_dense_mfma"] = {"seconds_per_solve": td,
+                                    "rk4_steps": [r.stats["steps"] for r in rd],
+                                    "max_abs_drho_vs_timed": err}
+        log(f"fp64 dense MFMA: {td:.3f} s/solve")
 
     if not args.no_mixed:
         for prec in ("bf16x3", "fp32"):
@@ -144,10 +175,13 @@ def main():
             tm = (time.perf_counter() - t0m) / len(OMEGAS)
             err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rm, results))
             pm, _ = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec=prec, reps=100)
+            peak = BF16_PEAK_TFLOPS / 3.0 if prec == "bf16x3" else FP32_PEAK_TFLOPS
             extra[f"mixed_{prec}"] = {
                 "seconds_per_solve": tm, "rk4_steps": [r.stats["steps"] for r in rm],
                 "folds": [r.stats["folds"] for r in rm],
                 "max_abs_drho_vs_fp64": err, "product_us": pm * 1e3,
+                "product_TFs_algorithmic": flops / (pm * 1e-3) / 1e12,
+                "product_frac": flops / (pm * 1e-3) / 1e12 / peak,
                 "speedup_vs_fp64": value / tm}
             log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
 
@@ -162,10 +196,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"ba{N}-m{M_BA}-s0 FP64 steady state, omega in {list(OMEGAS)}, "
-                               f"dt={DT}, tol={TOL}, rho0=I/N; value = seconds per solve",
+                               f"dt={DT}, tol={TOL}, rho0=I/N; value = seconds per solve "
+                               f"({'sparse' if sparse else 'dense'} product)",
                    "n": N, "omegas": list(OMEGAS), "tol": TOL, "dt": DT},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }

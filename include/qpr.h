@@ -106,6 +106,8 @@ typedef struct {
   int32_t* out_ptr;     /* n+1, CSR of out-links: row j lists a with j -> a    */
   int32_t* out_idx;     /* nnz_a                                              */
   double* pagerank;     /* n, stationary vector of G (power iteration)        */
+  int32_t* h_ptr;       /* n+1, CSR pattern of H_off (all values equal: +1 or -1) */
+  int32_t* h_idx;       /* nnz_h, ascending within a row                      */
   void* arena;
   size_t arena_bytes;
 } qpr_problem;
@@ -133,8 +135,16 @@ typedef struct {
   int32_t fold_every; /* mixed precision: steps between FP64 folds [=chunk]   */
   int32_t renorm;     /* mixed precision: divide by the trace at folds [1]    */
   int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1]  */
-  int32_t reserved[3];
+  int32_t product;    /* qpr_product [QPR_PRODUCT_AUTO]                       */
+  int32_t reserved[2];
 } qpr_opts;
+
+/* How the commutator product X = H_off rho is formed. */
+typedef enum {
+  QPR_PRODUCT_AUTO = 0,   /* sparse when H_off is below 5 % dense, else dense */
+  QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
+  QPR_PRODUCT_SPARSE = 2  /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
+} qpr_product;
 
 /* ------------------------------------------------------------------ build */
 
@@ -175,8 +185,8 @@ size_t qpr_workspace_bytes(int32_t n, int32_t prec);
  * Asynchronous.
  */
 qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho,
-                   double* out, int32_t prec, void* ws, size_t ws_bytes,
-                   qpr_stream_t stream);
+                   double* out, int32_t prec, const qpr_opts* opts, void* ws,
+                   size_t ws_bytes, qpr_stream_t stream);
 
 /*
  * nsteps classical RK4 steps of size dt (Supplementary Note 2) applied to rho
@@ -188,8 +198,8 @@ qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho,
  */
 qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt,
                         int32_t nsteps, double* rho, int32_t prec,
-                        double* diag_out, void* ws, size_t ws_bytes,
-                        qpr_stream_t stream);
+                        double* diag_out, const qpr_opts* opts, void* ws,
+                        size_t ws_bytes, qpr_stream_t stream);
 
 /*
  * Integrate from rho (in: rho0) until the first step n with
@@ -211,6 +221,35 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
                             double* rho, int32_t* rank, qpr_stats* stats,
                             const qpr_opts* opts, void* ws, size_t ws_bytes,
                             qpr_stream_t stream);
+
+/* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys). */
+size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec);
+
+/*
+ * Solve nsys independent systems (problem probs[k] at omega omegas[k]) to the
+ * steady state of Eq. (1) with RK4 (Supplementary Note 2) in shared launches:
+ * every stage kernel covers all running systems through a device-side
+ * (system, tile) work list; chunks of `opts->chunk` steps are replayed as one
+ * captured HIP graph, and between replays the lists are shrunk to the systems
+ * still running.  prec QPR_FP64 (product per opts->product) or QPR_FP32 (FP32
+ * MFMA product with the FP64 fold-and-judge defect correction of
+ * qpr_steady_state, judged every chunk).  The dense-product tile configuration
+ * is tuned on this batch's own work list unless opts->gemm_cfg >= 0.
+ *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are
+ *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
+ *           may be NULL or hold device int32[n_k] / NULL entries
+ *   stats   HOST qpr_stats[nsys] or NULL (per-system status in stats[k].status)
+ *   tuned_cfg  HOST int32 or NULL: the product configuration used (-1: none)
+ * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP, and after a
+ * full run QPR_E_NONFINITE / QPR_E_NOT_CONVERGED if any system failed.
+ * Synchronises once per chunk.
+ */
+qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* probs,
+                           const double* omegas, double dt, double tol,
+                           int64_t max_steps, int32_t prec, double* const* rhos,
+                           int32_t* const* ranks, qpr_stats* stats,
+                           const qpr_opts* opts, int32_t* tuned_cfg, void* ws,
+                           size_t ws_bytes, qpr_stream_t stream);
 
 /*
  * Rank nodes by descending p (device, n doubles), ties by ascending index,
@@ -274,7 +313,10 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * events: `reps` back-to-back launches of the commutator product
  * X = H_off [Re rho | Im rho] (the real products of the coherent term of
  * Eq. (1)) at precision `prec` with tile configuration `cfg` (-1 = default),
- * then `reps` launches of the fused stage-1 epilogue.
+ * then `reps` launches of the fused epilogue of an interior stage (reads
+ * Y_s, y_n and the accumulator, writes the accumulator and Y_{s+1}, plus X
+ * for the dense product).  cfg = -2 with QPR_FP64 times the sparse product
+ * (CSR gathers of rho through the pattern of H_off) in place of the dense one.
  *   rho     device, 2*n*n planar FP64 operand (unchanged)
  *   ms_out  HOST double[2]: mean milliseconds per product launch and per
  *           epilogue launch
@@ -284,6 +326,21 @@ qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32_t prec,
                             int32_t cfg, int32_t reps, const double* rho,
                             double* ms_out, void* ws, size_t ws_bytes,
                             qpr_stream_t stream);
+
+/*
+ * Autotuner: time every dense-product tile configuration at precision prec on
+ * P's padded size (`reps` launches each, HIP events on `stream`), make the
+ * fastest the default for that (precision, size) in this process and, if
+ * cache_path is not NULL, append "prec ld cfg microseconds name" to it.
+ *   best_cfg  host int32 or NULL;  us_out  host double[qpr_product_configs(prec)]
+ *             or NULL (-1 for configurations whose tile does not divide ld)
+ * Errors: QPR_E_ARG, QPR_E_WORKSPACE, QPR_E_HIP.  Synchronises.
+ */
+qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t reps,
+                        const char* cache_path, int32_t* best_cfg, double* us_out,
+                        void* ws, size_t ws_bytes, qpr_stream_t stream);
+/* Load a cache written by qpr_autotune (later lines win). */
+qpr_status qpr_load_tuning(const char* cache_path);
 
 /* Number of product tile configurations at precision prec, and their names. */
 int32_t qpr_product_configs(int32_t prec);

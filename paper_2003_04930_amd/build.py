@@ -26,6 +26,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep small per-thread arrays (prefetch registers) in VGPRs, not LDS
+    "-mllvm", "-disable-promote-alloca-to-lds",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 

@@ -1,0 +1,523 @@
+// Many independent (graph, omega) systems in one set of launches.
+//
+// Every kernel of an RK4 stage is launched once for the whole batch: a
+// persistent grid strides over a device-side list of (system, tile) items and
+// each item runs the same tile code as the single-system kernels.  A chunk of
+// steps (plus, in mixed precision, the FP64 fold and judge) is captured once as
+// a HIP graph and replayed; between replays the host reads every system's
+// control block and rewrites the item lists to the systems still running
+// (the lists live in device memory and their lengths are read by the kernels,
+// so the graph is never re-captured).
+//
+// Precision: FP64 (sparse or dense product, as for one system) or FP32
+// products with FP64 judging (the defect correction of the single solve).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+#include <vector>
+
+#include "qpr_common.h"
+#include "qpr_device.h"
+
+namespace qpr {
+namespace {
+
+constexpr int TE = 32;  // epilogue tile edge (matches the epilogue kernels)
+
+struct BatchFold {      // one system's fold: rho_a = (rho_a + delta) / tr, delta = 0
+  double *an_r, *an_i, *dn_r, *dn_i, *p_a, *p_n;
+  float *lo_r, *lo_i;
+  int n, ld, renorm;
+  DevState* st;
+};
+
+// st->aux[0] = tr(rho_a + delta) from the two diagonals; one item per system
+__global__ void __launch_bounds__(256) k_trace_batch(const BatchFold* __restrict__ f,
+                                                     const int* __restrict__ sys_list,
+                                                     const int* __restrict__ nsys) {
+  __shared__ double red[4];
+  const int ns = *nsys;
+  for (int it = blockIdx.x; it < ns; it += gridDim.x) {
+    const BatchFold& F = f[sys_list[it]];
+    if (F.st->stop) continue;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < F.n; j += 256) s += F.p_a[j] + F.p_n[j];
+    s = block_sum(s, red, 4);
+    if (threadIdx.x == 0) F.st->aux[0] = s;
+    __syncthreads();
+  }
+}
+
+// fold per (system, row block of 32 rows); skipped once the system stopped
+__global__ void __launch_bounds__(256) k_fold_batch(const BatchFold* __restrict__ f,
+                                                    const int2* __restrict__ items,
+                                                    const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchFold& F = f[item.x];
+    if (F.st->stop) continue;
+    const double inv = F.renorm ? 1.0 / F.st->aux[0] : 1.0;
+    const int r0 = item.y * TE;
+    for (int e = threadIdx.x; e < TE * F.ld; e += 256) {
+      const int a = r0 + e / F.ld, b = e % F.ld;
+      const size_t o = (size_t)a * F.ld + b;
+      const double vr = (F.an_r[o] + F.dn_r[o]) * inv;
+      const double vi = (F.an_i[o] + F.dn_i[o]) * inv;
+      F.an_r[o] = vr;
+      F.an_i[o] = vi;
+      F.dn_r[o] = 0.0;
+      F.dn_i[o] = 0.0;
+      if (F.lo_r) {
+        F.lo_r[o] = 0.f;
+        F.lo_i[o] = 0.f;
+      }
+      if (a == b && a < F.n) {
+        F.p_a[a] = vr;
+        F.p_n[a] = 0.0;
+      }
+    }
+  }
+}
+
+struct SysInfo {
+  int n, ld;
+  size_t ws_off, ws_size;
+};
+
+struct BatchLayout {
+  std::vector<SysInfo> sys;
+  size_t states, gemm_args, epi_args, fold_args, items_g, items_e, items_f, items_s, sys_list,
+      counts, total;
+  size_t max_g, max_e, max_f, max_s;
+};
+
+BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
+  L.max_g = L.max_e = L.max_f = L.max_s = 0;
+  for (int s = 0; s < nsys; ++s) {
+    SysInfo si;
+    si.n = ns[s];
+    si.ld = pad_n(ns[s]);
+    si.ws_size = ws_bytes(ns[s], prec);
+    si.ws_off = take(si.ws_size);
+    L.sys.push_back(si);
+    const size_t tg = (size_t)(si.ld / gtile) * (si.ld / gtile);
+    L.max_g += std::max(tg, (size_t)(si.ld / 32) * (si.ld / 32));  // any batch tile size
+    L.max_e += (size_t)(si.ld / TE) * (si.ld / TE);
+    L.max_f += (size_t)(si.ld / TE);
+    L.max_s += (size_t)spmm_items_per_system(si.n, si.ld);
+  }
+  L.states = take((size_t)nsys * sizeof(DevState));
+  L.gemm_args = take((size_t)nsys * 5 * sizeof(BatchGemm));
+  L.epi_args = take((size_t)nsys * 5 * sizeof(BatchEpi));
+  L.fold_args = take((size_t)nsys * sizeof(BatchFold));
+  L.items_g = take(L.max_g * sizeof(int2));
+  L.items_e = take(L.max_e * sizeof(int2));
+  L.items_f = take(L.max_f * sizeof(int2));
+  L.items_s = take(L.max_s * sizeof(int2));
+  L.sys_list = take((size_t)nsys * sizeof(int));
+  L.counts = take(5 * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+}  // namespace qpr
+
+using namespace qpr;
+
+extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec) {
+  if (nsys < 1 || !n || (prec != QPR_FP64 && prec != QPR_FP32)) return 0;
+  for (int s = 0; s < nsys; ++s)
+    if (n[s] < 2) return 0;
+  return batch_layout(nsys, n, prec, 32).total;
+}
+
+extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* probs,
+                                      const double* omegas, double dt, double tol,
+                                      int64_t max_steps, int32_t prec, double* const* rhos,
+                                      int32_t* const* ranks, qpr_stats* stats,
+                                      const qpr_opts* opts, int32_t* tuned_cfg, void* ws,
+                                      size_t ws_bytes_, qpr_stream_t stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  clear_error();
+  if (nsys < 1) return fail(QPR_E_ARG, "nsys must be >= 1");
+  if (!probs || !omegas || !rhos) return fail(QPR_E_ARG, "probs, omegas and rhos must not be NULL");
+  if (prec != QPR_FP64 && prec != QPR_FP32)
+    return fail(QPR_E_ARG, "batched solve supports QPR_FP64 and QPR_FP32 (got %d)", prec);
+  if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive");
+  if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
+  if (!ws || ((uintptr_t)ws) % kAlign) return fail(QPR_E_ARG, "workspace must be 256-byte aligned");
+  qpr_opts o{};
+  o.chunk = 32;
+  o.use_graph = 1;
+  o.renorm = 1;
+  o.gemm_cfg = -1;
+  o.product = QPR_PRODUCT_AUTO;
+  if (opts) o = *opts;
+  if (o.chunk <= 0) o.chunk = 32;
+  std::vector<int> ns(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const qpr_problem* P = probs[s];
+    if (!P || P->n < 2 || P->ld != pad_n(P->n) || !P->h_off)
+      return fail(QPR_E_ARG, "system %d: not a built problem", s);
+    if (!(omegas[s] >= 0.0 && omegas[s] <= 1.0))
+      return fail(QPR_E_ARG, "system %d: omega must be in [0,1]", s);
+    if (!rhos[s]) return fail(QPR_E_ARG, "system %d: rho must not be NULL", s);
+    const double reach = dt * ((1.0 - omegas[s]) * (P->h_hi - P->h_lo) + 2.0 * omegas[s]);
+    if (!(dt > 0.0) || reach >= 2.8)
+      return fail(QPR_E_UNSTABLE, "system %d: dt=%g outside the RK4 stability bound", s, dt);
+    ns[s] = P->n;
+  }
+  const BatchLayout L = batch_layout(nsys, ns.data(), prec, 32);
+  if (ws_bytes_ < L.total)
+    return fail(QPR_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", ws_bytes_, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevState* states = (DevState*)(base + L.states);
+  BatchGemm* d_gemm = (BatchGemm*)(base + L.gemm_args);
+  BatchEpi* d_epi = (BatchEpi*)(base + L.epi_args);
+  BatchFold* d_fold = (BatchFold*)(base + L.fold_args);
+  int2* d_items_g = (int2*)(base + L.items_g);
+  int2* d_items_e = (int2*)(base + L.items_e);
+  int2* d_items_f = (int2*)(base + L.items_f);
+  int* d_sys_list = (int*)(base + L.sys_list);
+  int2* d_items_s = (int2*)(base + L.items_s);
+  int* d_counts = (int*)(base + L.counts);  // [gemm, epilogue, fold, systems, sparse]
+
+  const bool mixed = prec == QPR_FP32;
+  const int xk = mixed ? OP_F32 : OP_F64;
+  // products: FP64 steps and all judges may gather sparsely; FP32 steps are dense MFMA
+  auto sparse_for = [&](const qpr_problem* P) {
+    if (o.product == QPR_PRODUCT_DENSE) return false;
+    if (o.product == QPR_PRODUCT_SPARSE) return true;
+    return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
+  };
+  const bool step_sparse = !mixed && sparse_for(probs[0]);
+  const bool judge_sparse = sparse_for(probs[0]);
+
+  // host argument tables: stage kinds 0..3 = RK4 stages, 4 = judge / RHS
+  std::vector<Ws> W(nsys);
+  std::vector<BatchGemm> hg((size_t)nsys * 5);
+  std::vector<BatchEpi> he((size_t)nsys * 5);
+  std::vector<BatchFold> hf(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    const qpr_problem* P = probs[k];
+    Ws& w = W[k];
+    if (!ws_carve(base + L.sys[k].ws_off, L.sys[k].ws_size, P->n, prec, &w))
+      return fail(QPR_E_WORKSPACE, "system %d: workspace carve failed", k);
+    w.st = states + k;
+    const ProbView pv = view_of(P);
+    struct St {
+      double *inr, *ini, *pin, *outr, *outi, *pout, cdt;
+    };
+    const St stg[4] = {{w.yn_r, w.yn_i, w.p_n, w.y1_r, w.y1_i, w.p_1, 0.5 * dt},
+                       {w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, w.p_2, 0.5 * dt},
+                       {w.y2_r, w.y2_i, w.p_2, w.y1_r, w.y1_i, w.p_1, dt},
+                       {w.y1_r, w.y1_i, w.p_1, w.yn_r, w.yn_i, w.p_n, dt / 6.0}};
+    for (int q = 0; q < 5; ++q) {
+      BatchGemm& g = hg[(size_t)q * nsys + k];
+      BatchEpi& e = he[(size_t)q * nsys + k];
+      g = BatchGemm{};
+      e = BatchEpi{};
+      e.pv = pv;
+      e.st = w.st;
+      e.partials = w.partials;
+      EpiArgs& a = e.a;
+      a.xr = w.x_r;
+      a.xi = w.x_i;
+      a.xfr = w.xf_r;
+      a.xfi = w.xf_i;
+      a.omega = omegas[k];
+      if (q < 4) {
+        const St& sg = stg[q];
+        g.H = mixed ? (const void*)P->h_off_f32 : (const void*)P->h_off;
+        g.yr = mixed ? (const void*)w.lo_r : (const void*)sg.inr;
+        g.yi = mixed ? (const void*)w.lo_i : (const void*)sg.ini;
+        g.xr = mixed ? (void*)w.xf_r : (void*)w.x_r;
+        g.xi = mixed ? (void*)w.xf_i : (void*)w.x_i;
+        g.ld = P->ld;
+        g.gate = mixed ? 1 : 0;
+        g.st = w.st;
+        a.ysr = sg.inr;
+        a.ysi = sg.ini;
+        a.ps = sg.pin;
+        a.ynr = w.yn_r;
+        a.yni = w.yn_i;
+        a.accr = w.acc_r;
+        a.acci = w.acc_i;
+        a.outr = sg.outr;
+        a.outi = sg.outi;
+        a.pout = sg.pout;
+        a.rar = mixed ? w.ra_r : nullptr;
+        a.rai = mixed ? w.ra_i : nullptr;
+        a.lor = mixed ? w.lo_r : nullptr;
+        a.loi = mixed ? w.lo_i : nullptr;
+        a.cdt = sg.cdt;
+        a.mode = EPI_S1 + q;
+        a.xkind = mixed ? XS_DENSE32 : step_sparse ? XS_SPARSE64 : XS_DENSE64;
+        a.check = q == 0 ? (mixed ? CHK_DELTA : CHK_PLAIN) : CHK_NONE;
+        a.gate = mixed ? 1 : 0;
+      } else {  // judge: r_a = L(rho_a) with the FP64 product
+        g.H = P->h_off;
+        g.yr = w.an_r;
+        g.yi = w.an_i;
+        g.xr = w.x_r;
+        g.xi = w.x_i;
+        g.ld = P->ld;
+        g.gate = 0;
+        g.st = w.st;
+        a.ysr = w.an_r;
+        a.ysi = w.an_i;
+        a.ps = w.p_a;
+        a.outr = w.ra_r;
+        a.outi = w.ra_i;
+        a.mode = EPI_RHS;
+        a.xkind = judge_sparse ? XS_SPARSE64 : XS_DENSE64;
+        a.check = CHK_JUDGE;
+      }
+    }
+    hf[k] = BatchFold{w.an_r, w.an_i, w.yn_r, w.yn_i, w.p_a, w.p_n,
+                      mixed ? w.lo_r : nullptr, mixed ? w.lo_i : nullptr,
+                      P->n, P->ld, o.renorm ? 1 : 0, w.st};
+  }
+  QPR_HIP(hipMemcpyAsync(d_gemm, hg.data(), hg.size() * sizeof(BatchGemm), hipMemcpyHostToDevice, s));
+  QPR_HIP(hipMemcpyAsync(d_epi, he.data(), he.size() * sizeof(BatchEpi), hipMemcpyHostToDevice, s));
+  QPR_HIP(hipMemcpyAsync(d_fold, hf.data(), hf.size() * sizeof(BatchFold), hipMemcpyHostToDevice, s));
+
+  // initial state of every system
+  for (int k = 0; k < nsys; ++k) {
+    const qpr_problem* P = probs[k];
+    Ws& w = W[k];
+    QPR_HIP(launch_state_init(w.st, tol, max_steps, mixed ? CHK_DELTA : CHK_PLAIN, s));
+    if (mixed) {
+      const size_t plane = (size_t)P->ld * P->ld;
+      QPR_HIP(launch_pad_in(rhos[k], P->n, P->ld, w.an_r, w.an_i, w.p_a, s));
+      QPR_HIP(launch_fill(w.yn_r, 2 * plane * 8, s));
+      QPR_HIP(launch_fill(w.p_n, (size_t)P->ld * 8, s));
+      QPR_HIP(launch_fill(w.lo_r, 2 * plane * 4, s));
+    } else {
+      QPR_HIP(launch_pad_in(rhos[k], P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
+    }
+  }
+
+  // work lists, largest systems first
+  std::vector<int> order(nsys);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+  int gtile = 64;
+  int gcfg = -1;
+  std::vector<int2> ig, ie, iff, isp;
+  std::vector<int> sl;
+  std::vector<char> active(nsys, 1);
+  auto build_lists = [&]() {
+    ig.clear();
+    ie.clear();
+    iff.clear();
+    isp.clear();
+    sl.clear();
+    for (int k : order) {
+      if (!active[k]) continue;
+      const int ld = pad_n(ns[k]);
+      const int tg = (ld / gtile) * (ld / gtile), te = (ld / TE) * (ld / TE);
+      for (int t = 0; t < tg; ++t) ig.push_back(make_int2(k, t));
+      for (int t = 0; t < te; ++t) ie.push_back(make_int2(k, t));
+      for (int t = 0; t < ld / TE; ++t) iff.push_back(make_int2(k, t));
+      const int ts = spmm_items_per_system(ns[k], ld);
+      for (int t = 0; t < ts; ++t) isp.push_back(make_int2(k, t));
+      sl.push_back(k);
+    }
+  };
+  int* h_counts = nullptr;
+  QPR_HIP(hipHostMalloc((void**)&h_counts, 5 * sizeof(int), hipHostMallocDefault));
+  auto upload_lists = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(d_items_g, ig.data(), ig.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_items_e, ie.data(), ie.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_items_f, iff.data(), iff.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_sys_list, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_items_s, isp.data(), isp.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    h_counts[0] = (int)ig.size();
+    h_counts[1] = (int)ie.size();
+    h_counts[2] = (int)iff.size();
+    h_counts[3] = (int)sl.size();
+    h_counts[4] = (int)isp.size();
+    if (e == hipSuccess) e = hipMemcpyAsync(d_counts, h_counts, 5 * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors are reused
+    return e;
+  };
+
+  const bool use_gemm = mixed || !step_sparse;
+  const int grid_g = 1024, grid_e = 2048, grid_f = 1024;
+  // tile configuration: tuned on this batch's own work list unless given
+  int cands[8];
+  const int ncand = batch_gemm_cfgs(xk, cands, 8);
+  if (use_gemm) {
+    if (o.gemm_cfg >= 0 && o.gemm_cfg < ncand) {
+      gcfg = cands[o.gemm_cfg];
+    } else {
+      hipEvent_t e0, e1;
+      QPR_HIP(hipEventCreate(&e0));
+      QPR_HIP(hipEventCreate(&e1));
+      float best = 1e30f;
+      for (int c = 0; c < ncand; ++c) {
+        // a dense FP64 judge shares the item list, so it needs 64-wide tiles
+        if (mixed && !judge_sparse && batch_gemm_tile(cands[c]) != 64) continue;
+        gtile = batch_gemm_tile(cands[c]);
+        build_lists();
+        QPR_HIP(upload_lists());
+        QPR_HIP(launch_gemm_batch(cands[c], d_gemm, d_items_g, d_counts, grid_g, s));
+        QPR_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r)
+          QPR_HIP(launch_gemm_batch(cands[c], d_gemm, d_items_g, d_counts, grid_g, s));
+        QPR_HIP(hipEventRecord(e1, s));
+        QPR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        QPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          gcfg = cands[c];
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+    }
+    gtile = batch_gemm_tile(gcfg);
+  }
+  if (tuned_cfg) *tuned_cfg = gcfg;
+  build_lists();
+  QPR_HIP(upload_lists());
+
+  auto enqueue_stage = [&](int q, hipStream_t qs) -> hipError_t {
+    hipError_t e = hipSuccess;
+    const bool judge = q == 4;
+    const bool gemm = judge ? !judge_sparse : use_gemm;
+    const bool spmm = judge ? judge_sparse : step_sparse;
+    if (spmm) {
+      e = launch_spmm_batch(d_epi + (size_t)q * nsys, d_items_s, d_counts + 4, grid_e, qs);
+      if (e != hipSuccess) return e;
+    }
+    if (gemm) {
+      // the judge always takes the FP64 product (configuration 0 of the FP64 batch table)
+      const int cfg = judge ? 0 : gcfg;
+      e = launch_gemm_batch(cfg, d_gemm + (size_t)q * nsys, d_items_g, d_counts, grid_g, qs);
+      if (e != hipSuccess) return e;
+    }
+    const int xs = judge ? (judge_sparse ? XS_SPARSE64 : XS_DENSE64)
+                         : mixed ? XS_DENSE32 : step_sparse ? XS_SPARSE64 : XS_DENSE64;
+    return launch_epilogue_batch(xs, d_epi + (size_t)q * nsys, d_items_e, d_counts + 1, grid_e, qs);
+  };
+  auto enqueue_fold_judge = [&](hipStream_t qs) -> hipError_t {
+    k_trace_batch<<<256, 256, 0, qs>>>(d_fold, d_sys_list, d_counts + 3);
+    k_fold_batch<<<grid_f, 256, 0, qs>>>(d_fold, d_items_f, d_counts + 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return enqueue_stage(4, qs);
+  };
+  if (mixed && !judge_sparse && gtile != 64)
+    return fail(QPR_E_ARG, "dense FP64 judging needs a 64-wide product tile configuration");
+  if (mixed) QPR_HIP(enqueue_fold_judge(s));  // fold of delta = 0: renormalise + judge rho0
+
+  auto enqueue_chunk = [&](hipStream_t qs) -> hipError_t {
+    for (int k = 0; k < o.chunk; ++k)
+      for (int q = 0; q < 4; ++q) {
+        hipError_t e = enqueue_stage(q, qs);
+        if (e != hipSuccess) return e;
+      }
+    return mixed ? enqueue_fold_judge(qs) : hipSuccess;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;
+  if (o.use_graph) {
+    QPR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    QPR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_chunk(cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    QPR_HIP(e);
+    QPR_HIP(e2);
+    QPR_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  std::vector<DevState> hs(nsys);
+  qpr_status rc = QPR_OK;
+  for (;;) {
+    hipError_t e = o.use_graph ? hipGraphLaunch(exec, s) : enqueue_chunk(s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hs.data(), states, nsys * sizeof(DevState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = fail(QPR_E_HIP, "batched chunk failed: %s", hipGetErrorString(e));
+      break;
+    }
+    int running = 0;
+    bool changed = false;
+    for (int k = 0; k < nsys; ++k) {
+      const bool a = hs[k].stop == 0;
+      if (!a && active[k]) {
+        active[k] = 0;
+        changed = true;
+      }
+      running += a;
+    }
+    if (!running) break;
+    if (changed) {
+      build_lists();
+      e = upload_lists();
+      if (e != hipSuccess) {
+        rc = fail(QPR_E_HIP, "work-list upload failed: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (cs) hipStreamDestroy(cs);
+  hipHostFree(h_counts);
+  if (rc != QPR_OK) return rc;
+
+  // results: state, ranking and diagnostics per system
+  int n_bad = 0, n_unconv = 0;
+  for (int k = 0; k < nsys; ++k) {
+    const qpr_problem* P = probs[k];
+    Ws& w = W[k];
+    double* outr = mixed ? w.an_r : w.yn_r;
+    double* outi = mixed ? w.an_i : w.yn_i;
+    double* outp = mixed ? w.p_a : w.p_n;
+    const DevState& f = hs[k];
+    if (!f.nonfinite) {
+      QPR_HIP(launch_state_stats(outr, outi, outp, P->n, P->ld, w, s));
+      QPR_HIP(launch_pad_out(outr, outi, P->n, P->ld, rhos[k], s));
+      if (ranks && ranks[k] && f.converged) QPR_HIP(launch_rank(P->n, outp, ranks[k], s));
+    }
+  }
+  QPR_HIP(hipMemcpyAsync(hs.data(), states, nsys * sizeof(DevState), hipMemcpyDeviceToHost, s));
+  QPR_HIP(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int k = 0; k < nsys; ++k) {
+    const DevState& f = hs[k];
+    n_bad += f.nonfinite != 0;
+    n_unconv += !f.converged;
+    if (!stats) continue;
+    qpr_stats& S = stats[k];
+    S = qpr_stats{};
+    S.steps = f.converged ? f.conv_step : f.step;
+    S.folds = f.folds;
+    S.rhs_evals_fp64 = mixed ? f.folds : 4 * S.steps + 1;
+    S.rhs_evals = 4 * S.steps + (mixed ? f.folds : 1);
+    S.t = (double)S.steps * dt;
+    S.residual = std::sqrt(mixed ? f.judge2 : f.resid2);
+    S.trace_err = std::fabs(f.aux[0] - 1.0);
+    S.herm_err = f.aux[1];
+    S.min_diag = f.aux[2];
+    S.seconds = secs;
+    S.converged = f.converged;
+    S.status = f.nonfinite ? QPR_E_NONFINITE : f.converged ? QPR_OK : QPR_E_NOT_CONVERGED;
+  }
+  if (n_bad) return fail(QPR_E_NONFINITE, "%d systems met non-finite values", n_bad);
+  if (n_unconv) return fail(QPR_E_NOT_CONVERGED, "%d systems did not converge", n_unconv);
+  return QPR_OK;
+}

@@ -24,7 +24,7 @@ struct Summary {          // device -> host after the build
 
 struct ArenaLayout {
   size_t h64, h32, h16, a8, at8, hdiag, d, inv_out, pr, pr_tmp, dang, outdeg,
-      indeg, degh, in_ptr, out_ptr, in_idx, out_idx, edges, summary, total;
+      indeg, degh, in_ptr, out_ptr, h_ptr, in_idx, out_idx, h_idx, edges, summary, total;
 };
 
 ArenaLayout arena_layout(int n, long long n_edges) {
@@ -49,8 +49,10 @@ ArenaLayout arena_layout(int n, long long n_edges) {
   L.degh = take(ld * 4);
   L.in_ptr = take((ld + 1) * 4);
   L.out_ptr = take((ld + 1) * 4);
+  L.h_ptr = take((ld + 1) * 4);
   L.in_idx = take(e * 4);
   L.out_idx = take(e * 4);
+  L.h_idx = take(2 * e * 4);
   L.edges = take(2 * e * 4);
   L.summary = take(sizeof(Summary));
   L.total = o;
@@ -112,12 +114,13 @@ __global__ void __launch_bounds__(256) k_rows(const unsigned char* __restrict__ 
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ indeg,
                                                const int* __restrict__ outdeg,
                                                const int* __restrict__ degh, int n,
-                                               int* in_ptr, int* out_ptr, Summary* sm) {
+                                               int* in_ptr, int* out_ptr, int* h_ptr,
+                                               Summary* sm) {
   __shared__ long long buf[1024];
   const int t = threadIdx.x;
-  for (int which = 0; which < 2; ++which) {
-    const int* deg = which == 0 ? indeg : outdeg;
-    int* ptr = which == 0 ? in_ptr : out_ptr;
+  for (int which = 0; which < 3; ++which) {
+    const int* deg = which == 0 ? indeg : which == 1 ? outdeg : degh;
+    int* ptr = which == 0 ? in_ptr : which == 1 ? out_ptr : h_ptr;
     long long carry = 0;
     for (int base = 0; base < n; base += 1024) {
       const int i = base + t;
@@ -153,23 +156,28 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ indeg,
   if (t == 0) sm->nnz_h = buf[0];
 }
 
-// One wave per row: ascending CSR fill of in-links (row a of A8) and
-// out-links (row j of AT8) by ballot compaction.
+// One wave per row: ascending CSR fill of in-links (row a of A8), out-links
+// (row a of AT8) and the off-diagonal Hamiltonian pattern (A8 | AT8 without
+// the diagonal) by ballot compaction.
 __global__ void __launch_bounds__(256) k_fill_csr(const unsigned char* __restrict__ A8,
                                                   const unsigned char* __restrict__ AT8,
                                                   int n, int ld, const int* __restrict__ in_ptr,
-                                                  const int* __restrict__ out_ptr, int* in_idx,
-                                                  int* out_idx) {
+                                                  const int* __restrict__ out_ptr,
+                                                  const int* __restrict__ h_ptr, int* in_idx,
+                                                  int* out_idx, int* h_idx) {
   const int lane = threadIdx.x & 63;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (a >= n) return;
-  for (int which = 0; which < 2; ++which) {
-    const unsigned char* M = which == 0 ? A8 : AT8;
-    int* idx = which == 0 ? in_idx : out_idx;
-    int pos = which == 0 ? in_ptr[a] : out_ptr[a];
+  for (int which = 0; which < 3; ++which) {
+    int* idx = which == 0 ? in_idx : which == 1 ? out_idx : h_idx;
+    int pos = which == 0 ? in_ptr[a] : which == 1 ? out_ptr[a] : h_ptr[a];
     for (int b0 = 0; b0 < n; b0 += 64) {
       const int b = b0 + lane;
-      const int x = b < n ? M[(size_t)a * ld + b] : 0;
+      int x = 0;
+      if (b < n) {
+        const int u = A8[(size_t)a * ld + b], v = AT8[(size_t)a * ld + b];
+        x = which == 0 ? u : which == 1 ? v : ((u | v) && b != a);
+      }
       const unsigned long long mask = __ballot(x);
       const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
       if (x) idx[pos + __popcll(below)] = b;
@@ -328,6 +336,8 @@ extern "C" qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t
   P.out_ptr = (int32_t*)(base + L.out_ptr);
   P.in_idx = (int32_t*)(base + L.in_idx);
   P.out_idx = (int32_t*)(base + L.out_idx);
+  P.h_ptr = (int32_t*)(base + L.h_ptr);
+  P.h_idx = (int32_t*)(base + L.h_idx);
   P.pagerank = (double*)(base + L.pr);
   P.arena = arena;
   P.arena_bytes = arena_bytes;
@@ -351,10 +361,10 @@ extern "C" qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t
   k_rows<<<(ld + 3) / 4, 256, 0, s>>>(A8, AT8, n, ld, hsign, P.h_off, P.h_off_f32,
                                       P.h_off_bf16, P.indeg, P.outdeg, degh);
   QPR_HIP(hipGetLastError());
-  k_scan<<<1, 1024, 0, s>>>(P.indeg, P.outdeg, degh, n, P.in_ptr, P.out_ptr, sm);
+  k_scan<<<1, 1024, 0, s>>>(P.indeg, P.outdeg, degh, n, P.in_ptr, P.out_ptr, P.h_ptr, sm);
   QPR_HIP(hipGetLastError());
-  k_fill_csr<<<(n + 3) / 4, 256, 0, s>>>(A8, AT8, n, ld, P.in_ptr, P.out_ptr, P.in_idx,
-                                         P.out_idx);
+  k_fill_csr<<<(n + 3) / 4, 256, 0, s>>>(A8, AT8, n, ld, P.in_ptr, P.out_ptr, P.h_ptr,
+                                         P.in_idx, P.out_idx, P.h_idx);
   QPR_HIP(hipGetLastError());
   k_vectors<<<1, 1024, 0, s>>>(P.outdeg, degh, n, alpha, teleport, hdiag, P.inv_outdeg,
                                P.dangling, P.d, P.h_diag, sm);

@@ -89,6 +89,8 @@ struct ProbView {
   double alpha;
   const double *h, *d, *inv_outdeg;
   const int *dangling, *in_ptr, *in_idx;
+  int hsign;                 // value of every nonzero of H_off (+1 or -1)
+  const int *h_ptr, *h_idx;  // CSR pattern of H_off
 };
 ProbView view_of(const qpr_problem* P);
 
@@ -96,6 +98,13 @@ enum EpiMode { EPI_RHS = 0, EPI_S1 = 1, EPI_S2 = 2, EPI_S3 = 3, EPI_S4 = 4 };
 
 // Which buffer kind the epilogue reads X from and what lowp copy it writes.
 enum OpKind { OP_F64 = 0, OP_F32 = 1, OP_BF16X3 = 2 };
+
+// Where the epilogue gets X = H_off Y from.
+enum XSource {
+  XS_DENSE64 = 0,   // FP64 X written by the dense product
+  XS_DENSE32 = 1,   // FP32 X written by a low-precision dense product
+  XS_SPARSE64 = 2   // FP64 X written by the sparse product (k_spmm)
+};
 
 struct EpiArgs {
   const double *xr, *xi;      // FP64 X (OP_F64)
@@ -110,7 +119,7 @@ struct EpiArgs {
   float *lor, *loi;           // FP32 copy of the output state (or null)
   uint16_t* slices;           // bf16 slices of the output state (or null)
   double omega, cdt;          // cdt: c_s * dt for stages 1..3, dt/6 for stage 4
-  int mode, xkind;
+  int mode, xkind;             // xkind: XSource
   int check;                  // CheckMode
   int gate;                   // 1: also return when DevState::hold is set
 };
@@ -138,8 +147,37 @@ hipError_t launch_fill(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_scale_planes(double* r, double* i, double* p, int n, int ld,
                                const DevState* st, hipStream_t s);
 
+// One system's operands for a batched product launch (pointer types per kind).
+struct BatchGemm {
+  const void *H, *yr, *yi;
+  void *xr, *xi;
+  int ld, gate;
+  const DevState* st;
+};
+// One system's arguments for a batched epilogue launch.
+struct BatchEpi {
+  ProbView pv;
+  EpiArgs a;
+  DevState* st;
+  double* partials;
+};
+int batch_gemm_cfgs(int kind, int* out, int max);
+const char* batch_gemm_name(int cfg);
+int batch_gemm_tile(int cfg);
+hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,
+                             const int* nitems, int grid, hipStream_t s);
+hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* items,
+                                 const int* nitems, int grid, hipStream_t s);
+hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
+                       double* xi, const DevState* st, int gate, hipStream_t s);
+int spmm_items_per_system(int n, int ld);
+hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
+                             hipStream_t s);
+
 int gemm_num_cfgs(int kind);
 const char* gemm_cfg_name(int kind, int cfg);
 int gemm_default_cfg(int kind, int n);
+void gemm_set_tuned(int kind, int ld, int cfg);
+bool gemm_cfg_fits(int kind, int cfg, int ld);
 
 }  // namespace qpr

@@ -12,6 +12,9 @@
 // Tiles are staged through LDS with double buffering (global loads of tile
 // k+1 are in flight while tile k is multiplied).
 #include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "qpr_common.h"
 #include "qpr_device.h"
@@ -60,29 +63,24 @@ struct MfmaK4<float> {
   static __device__ __forceinline__ int out_row(int r, int lr) { return 4 * lr + r; }
 };
 
-template <typename T, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
-    k_gemm_k4(const T* __restrict__ H, const T* __restrict__ Yr, const T* __restrict__ Yi,
-              T* __restrict__ Xr, T* __restrict__ Xi, int ld, const DevState* __restrict__ st,
-              int gate) {
+// One BM x BN output tile (both planes) at (m0, n0).
+template <typename T, int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ void gemm_k4_tile(const T* __restrict__ H, const T* __restrict__ Yr,
+                                             const T* __restrict__ Yi, T* __restrict__ Xr,
+                                             T* __restrict__ Xi, int ld, int m0, int n0) {
   typedef MfmaK4<T> M;
   typedef typename M::acc_t acc_t;
   typedef typename M::vec_t vec_t;
   constexpr int EV = M::EV;
   constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
-  constexpr int BK = 16;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int AP = BM + EV, BP = BN + EV;
   constexpr int NA = BK * BM / EV / NT, NB = BK * BN / EV / NT;
   static_assert(NA * NT * EV == BK * BM && NB * NT * EV == BK * BN, "tile/thread mismatch");
   __shared__ T As[2][BK * AP];
   __shared__ T Bs[2][2][BK * BP];
-  if (st->stop || (gate && st->hold)) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_m = ld / BM;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int m0 = (logical % tiles_m) * BM, n0 = (logical / tiles_m) * BN;
   const int wm0 = (wave % NWM) * WM, wn0 = (wave / NWM) * WN;
 
   acc_t acc[2][FM][FN];
@@ -166,6 +164,39 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
           const int col = n0 + wn0 + j * 16 + lc;
           X[(size_t)row * ld + col] = acc[p][i][j][r];
         }
+  }
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int BK = 16>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_k4(const T* __restrict__ H, const T* __restrict__ Yr, const T* __restrict__ Yi,
+              T* __restrict__ Xr, T* __restrict__ Xi, int ld, const DevState* __restrict__ st,
+              int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  gemm_k4_tile<T, BM, BN, WM, WN, BK>(H, Yr, Yi, Xr, Xi, ld, (logical % tiles_m) * BM,
+                                      (logical / tiles_m) * BN);
+}
+
+// Persistent form for many systems: the grid strides over a device-side list
+// of (system, tile) items; a system whose control block says stop (or hold,
+// when gated) is skipped.  The item count is read from device memory so the
+// host can shrink the list between replays of a captured graph.
+template <typename T, int BM, int BN, int WM, int WN, int BK = 16>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_k4_batch(const BatchGemm* __restrict__ args, const int2* __restrict__ items,
+                    const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchGemm& g = args[item.x];
+    if (g.st->stop || (g.gate && g.st->hold)) continue;
+    const int tiles_m = g.ld / BM;
+    gemm_k4_tile<T, BM, BN, WM, WN, BK>((const T*)g.H, (const T*)g.yr, (const T*)g.yi,
+                                        (T*)g.xr, (T*)g.xi, g.ld, (item.y % tiles_m) * BM,
+                                        (item.y / tiles_m) * BN);
+    __syncthreads();
   }
 }
 
@@ -296,17 +327,23 @@ typedef void (*F32Fn)(const float*, const float*, const float*, float*, float*, 
 typedef void (*BFFn)(const uint16_t*, const uint16_t*, float*, float*, int, const DevState*, int);
 
 const GemmCfg<F64Fn> kF64[] = {
-    {64, 64, "f64_64x64_w32x32", k_gemm_k4<double, 64, 64, 32, 32>, 256},
-    {32, 32, "f64_32x32_w16x16", k_gemm_k4<double, 32, 32, 16, 16>, 256},
-    {128, 64, "f64_128x64_w64x32", k_gemm_k4<double, 128, 64, 64, 32>, 256},
-    {64, 128, "f64_64x128_w32x64", k_gemm_k4<double, 64, 128, 32, 64>, 256},
-    {64, 64, "f64_64x64_w64x32", k_gemm_k4<double, 64, 64, 64, 32>, 128},
+    {64, 64, "f64_64x64_w32x32_k16", k_gemm_k4<double, 64, 64, 32, 32>, 256},
+    {32, 32, "f64_32x32_w16x16_k16", k_gemm_k4<double, 32, 32, 16, 16>, 256},
+    {128, 64, "f64_128x64_w64x32_k16", k_gemm_k4<double, 128, 64, 64, 32>, 256},
+    {64, 128, "f64_64x128_w32x64_k16", k_gemm_k4<double, 64, 128, 32, 64>, 256},
+    {64, 64, "f64_64x64_w64x32_k16", k_gemm_k4<double, 64, 64, 64, 32>, 128},
+    {64, 64, "f64_64x64_w32x32_k32", k_gemm_k4<double, 64, 64, 32, 32, 32>, 256},
+    {32, 32, "f64_32x32_w16x16_k32", k_gemm_k4<double, 32, 32, 16, 16, 32>, 256},
+    {64, 32, "f64_64x32_w32x16_k32", k_gemm_k4<double, 64, 32, 32, 16, 32>, 256},
+    {32, 64, "f64_32x64_w16x32_k32", k_gemm_k4<double, 32, 64, 16, 32, 32>, 256},
 };
 const GemmCfg<F32Fn> kF32[] = {
-    {64, 64, "f32_64x64_w32x32", k_gemm_k4<float, 64, 64, 32, 32>, 256},
-    {32, 32, "f32_32x32_w32x32", k_gemm_k4<float, 32, 32, 32, 32>, 64},
-    {128, 64, "f32_128x64_w64x32", k_gemm_k4<float, 128, 64, 64, 32>, 256},
-    {64, 64, "f32_64x64_w64x32", k_gemm_k4<float, 64, 64, 64, 32>, 128},
+    {64, 64, "f32_64x64_w32x32_k16", k_gemm_k4<float, 64, 64, 32, 32>, 256},
+    {32, 32, "f32_32x32_w32x32_k16", k_gemm_k4<float, 32, 32, 32, 32>, 64},
+    {128, 64, "f32_128x64_w64x32_k16", k_gemm_k4<float, 128, 64, 64, 32>, 256},
+    {64, 64, "f32_64x64_w64x32_k16", k_gemm_k4<float, 64, 64, 64, 32>, 128},
+    {64, 64, "f32_64x64_w32x32_k32", k_gemm_k4<float, 64, 64, 32, 32, 32>, 256},
+    {32, 32, "f32_32x32_w16x16_k32", k_gemm_k4<float, 32, 32, 16, 16, 32>, 256},
 };
 const GemmCfg<BFFn> kBF[] = {
     {64, 64, "bf16x3_64x64_w32x32", k_gemm_bf16x3<64, 64, 32, 32>, 256},
@@ -324,22 +361,70 @@ int gemm_num_cfgs(int kind) {
   return kind == OP_F64 ? kNumF64 : kind == OP_F32 ? kNumF32 : kind == OP_BF16X3 ? kNumBF : 0;
 }
 
+bool gemm_cfg_fits(int kind, int cfg, int ld) {
+  if (cfg < 0 || cfg >= gemm_num_cfgs(kind)) return false;
+  int bm, bn;
+  if (kind == OP_F64) {
+    bm = kF64[cfg].bm;
+    bn = kF64[cfg].bn;
+  } else if (kind == OP_F32) {
+    bm = kF32[cfg].bm;
+    bn = kF32[cfg].bn;
+  } else {
+    bm = kBF[cfg].bm;
+    bn = kBF[cfg].bn;
+  }
+  return ld % bm == 0 && ld % bn == 0;
+}
+
 const char* gemm_cfg_name(int kind, int cfg) {
   if (cfg < 0 || cfg >= gemm_num_cfgs(kind)) return "?";
   return kind == OP_F64 ? kF64[cfg].name : kind == OP_F32 ? kF32[cfg].name : kBF[cfg].name;
 }
 
+// Tile choice per (kind, padded size): filled by the autotuner (qpr_autotune)
+// or a tuning cache; configuration 0 otherwise.
+namespace {
+struct TuneEntry {
+  int kind, ld, cfg;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+}  // namespace
+
+void gemm_set_tuned(int kind, int ld, int cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.kind == kind && e.ld == ld) {
+      e.cfg = cfg;
+      return;
+    }
+  g_tune.push_back({kind, ld, cfg});
+}
+
 int gemm_default_cfg(int kind, int n) {
-  (void)kind;
-  (void)n;
-  return 0;
+  const int ld = pad_n(n);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int best = -1, best_ld = 0;
+  for (const auto& e : g_tune)  // exact size, else the nearest tuned size of the same kind
+    if (e.kind == kind && (best < 0 || std::abs(e.ld - ld) < std::abs(best_ld - ld))) {
+      best = e.cfg;
+      best_ld = e.ld;
+    }
+  if (best >= 0) return best;
+  // untuned defaults, from HIP-event sweeps on MI355X at N = 922, 2048, 4096:
+  // small problems want more, smaller tiles; large ones 128-row tiles
+  const bool big = ld >= 2048 && ld % 128 == 0;
+  if (kind == OP_F64) return big ? 2 : 1;
+  if (kind == OP_F32) return big ? 0 : 5;
+  return big ? 3 : 0;
 }
 
 template <typename C>
 static int pick(const C* table, int count, int cfg, int kind, int n, int ld) {
   if (cfg < 0 || cfg >= count) cfg = gemm_default_cfg(kind, n);
-  if (ld % table[cfg].bm || ld % table[cfg].bn) cfg = 0;  // config 0 tiles 64x64
-  return cfg;
+  if (cfg < 0 || cfg >= count || ld % table[cfg].bm || ld % table[cfg].bn) cfg = 0;
+  return cfg;  // configuration 0 tiles 64 x 64, which divides every ld
 }
 
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w, const double* yr,
@@ -365,6 +450,39 @@ hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w, con
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
+}
+
+typedef void (*F64BatchFn)(const BatchGemm*, const int2*, const int*);
+struct BatchCfg {
+  int kind, bm, bn, threads;
+  const char* name;
+  F64BatchFn fn;
+};
+const BatchCfg kBatch[] = {
+    {OP_F64, 64, 64, 256, "f64_64x64_w32x32_k16", k_gemm_k4_batch<double, 64, 64, 32, 32>},
+    {OP_F64, 64, 64, 256, "f64_64x64_w32x32_k32", k_gemm_k4_batch<double, 64, 64, 32, 32, 32>},
+    {OP_F64, 32, 32, 256, "f64_32x32_w16x16_k32", k_gemm_k4_batch<double, 32, 32, 16, 16, 32>},
+    {OP_F32, 64, 64, 256, "f32_64x64_w32x32_k16", (F64BatchFn)k_gemm_k4_batch<float, 64, 64, 32, 32>},
+    {OP_F32, 64, 64, 256, "f32_64x64_w32x32_k32", (F64BatchFn)k_gemm_k4_batch<float, 64, 64, 32, 32, 32>},
+    {OP_F32, 32, 32, 256, "f32_32x32_w16x16_k32", (F64BatchFn)k_gemm_k4_batch<float, 32, 32, 16, 16, 32>},
+};
+constexpr int kNumBatch = sizeof(kBatch) / sizeof(kBatch[0]);
+
+int batch_gemm_cfgs(int kind, int* out, int max) {
+  int c = 0;
+  for (int i = 0; i < kNumBatch; ++i)
+    if (kBatch[i].kind == kind && c < max) out[c++] = i;
+  return c;
+}
+const char* batch_gemm_name(int cfg) { return cfg >= 0 && cfg < kNumBatch ? kBatch[cfg].name : "?"; }
+int batch_gemm_tile(int cfg) { return cfg >= 0 && cfg < kNumBatch ? kBatch[cfg].bm : 64; }
+
+hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,
+                             const int* nitems, int grid, hipStream_t s) {
+  if (cfg < 0 || cfg >= kNumBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kBatch[cfg].fn, dim3(grid), dim3(kBatch[cfg].threads), 0, s, args, items,
+                     nitems);
+  return hipGetLastError();
 }
 
 }  // namespace qpr

@@ -40,6 +40,13 @@ qpr_status fail(qpr_status s, const char* fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
+// Sparse gathers for the FP64 product when H_off is sparse enough (or forced).
+static bool use_sparse(const qpr_problem* P, int product, int xk) {
+  if (xk != OP_F64 || product == QPR_PRODUCT_DENSE) return false;
+  if (product == QPR_PRODUCT_SPARSE) return true;
+  return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
+}
+
 static int op_kind(int prec) {
   return prec == QPR_FP32 ? OP_F32 : prec == QPR_BF16X3 ? OP_BF16X3 : OP_F64;
 }
@@ -165,9 +172,10 @@ static qpr_status check_dt(const qpr_problem* P, double omega, double dt) {
 // the low-precision copies the previous epilogue wrote, and `ra` (the FP64
 // anchor residual) is added to every stage's right-hand side.
 static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView& pv, double omega,
-                               double dt, int xk, int cfg, int check, bool with_ra,
+                               double dt, int xk, int cfg, int product, int check, bool with_ra,
                                hipStream_t s) {
   const int gate = check == CHK_DELTA ? 1 : 0;
+  const bool sparse = use_sparse(P, product, xk);
   struct Stage {
     double *inr, *ini, *pin, *outr, *outi, *pout;
     double cdt;
@@ -180,7 +188,8 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
   };
   for (int k = 0; k < 4; ++k) {
     const Stage& sg = stages[k];
-    hipError_t e = launch_gemm(xk, cfg, P, w, sg.inr, sg.ini, gate, s);
+    hipError_t e = sparse ? launch_spmm(pv, sg.inr, sg.ini, w.x_r, w.x_i, w.st, gate, s)
+                          : launch_gemm(xk, cfg, P, w, sg.inr, sg.ini, gate, s);
     if (e != hipSuccess) return e;
     EpiArgs a{};
     a.xr = w.x_r;
@@ -205,7 +214,7 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
     a.omega = omega;
     a.cdt = sg.cdt;
     a.mode = EPI_S1 + k;
-    a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+    a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
     a.check = k == 0 ? check : CHK_NONE;
     a.gate = gate;
     e = launch_epilogue(pv, a, w, s);
@@ -217,13 +226,17 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
 // L(Y) for Y in (inr, ini, pin) into (outr, outi); FP64 product unless xk says otherwise.
 static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView& pv, double omega,
                               double* inr, double* ini, double* pin, double* outr, double* outi,
-                              int xk, int cfg, int check, hipStream_t s) {
+                              int xk, int cfg, int product, int check, hipStream_t s) {
+  const bool sparse = use_sparse(P, product, xk);
   if (xk != OP_F64) {
     hipError_t e = launch_to_lowp(xk, inr, ini, P->n, P->ld, w, s);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch_gemm(xk, cfg, P, w, inr, ini, 0, s);
-  if (e != hipSuccess) return e;
+  {
+    hipError_t e = sparse ? launch_spmm(pv, inr, ini, w.x_r, w.x_i, w.st, 0, s)
+                          : launch_gemm(xk, cfg, P, w, inr, ini, 0, s);
+    if (e != hipSuccess) return e;
+  }
   EpiArgs a{};
   a.xr = w.x_r;
   a.xi = w.x_i;
@@ -236,7 +249,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
   a.outi = outi;
   a.omega = omega;
   a.mode = EPI_RHS;
-  a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+  a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
   a.check = check;
   return launch_epilogue(pv, a, w, s);
 }
@@ -253,8 +266,21 @@ extern "C" size_t qpr_workspace_bytes(int32_t n, int32_t prec) {
   return ws_bytes(n, prec);
 }
 
+static qpr_opts default_opts() {
+  qpr_opts o{};
+  o.chunk = 64;
+  o.use_graph = 1;
+  o.fold_every = 0;
+  o.renorm = 1;
+  o.gemm_cfg = -1;
+  o.product = QPR_PRODUCT_AUTO;
+  return o;
+}
+
 extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho, double* out,
-                              int32_t prec, void* ws, size_t wsb, qpr_stream_t stream) {
+                              int32_t prec, const qpr_opts* opts, void* ws, size_t wsb,
+                              qpr_stream_t stream) {
+  const qpr_opts o = opts ? *opts : default_opts();
   clear_error();
   Ws w;
   qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
@@ -265,15 +291,17 @@ extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* 
   const ProbView pv = view_of(P);
   QPR_HIP(launch_state_init(w.st, 0.0, 0, 0, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
-  QPR_HIP(enqueue_rhs(P, w, pv, omega, w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, op_kind(prec), -1,
-                        CHK_NONE, s));
+  QPR_HIP(enqueue_rhs(P, w, pv, omega, w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, op_kind(prec), o.gemm_cfg,
+                        o.product, CHK_NONE, s));
   QPR_HIP(launch_pad_out(w.y2_r, w.y2_i, P->n, P->ld, out, s));
   return QPR_OK;
 }
 
 extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt, int32_t nsteps,
-                                   double* rho, int32_t prec, double* diag_out, void* ws,
-                                   size_t wsb, qpr_stream_t stream) {
+                                   double* rho, int32_t prec, double* diag_out,
+                                   const qpr_opts* opts, void* ws, size_t wsb,
+                                   qpr_stream_t stream) {
+  const qpr_opts o = opts ? *opts : default_opts();
   clear_error();
   Ws w;
   qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
@@ -288,7 +316,7 @@ extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.yn_r, w.yn_i, P->n, P->ld, w, s));
   for (int k = 0; k < nsteps; ++k)
-    QPR_HIP(enqueue_step(P, w, pv, omega, dt, xk, -1, CHK_NONE, false, s));
+    QPR_HIP(enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, o.product, CHK_NONE, false, s));
   if (diag_out) {
     QPR_HIP(launch_state_stats(w.yn_r, w.yn_i, w.p_n, P->n, P->ld, w, s));
     // diag_out = [resid2, trace, herm, nonfinite]
@@ -380,8 +408,7 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive (got %g)", tol);
   if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
   if ((st = check_dt(P, omega, dt)) != QPR_OK) return st;
-  qpr_opts o{64, 1, 0, 1, -1, {0, 0, 0}};
-  if (opts) o = *opts;
+  qpr_opts o = opts ? *opts : default_opts();
   if (o.chunk <= 0) o.chunk = 64;
   if (o.fold_every <= 0) o.fold_every = o.chunk;
   hipStream_t s = (hipStream_t)stream;
@@ -401,7 +428,8 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
     QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
     auto chunk_fn = [&](hipStream_t q) -> hipError_t {
       for (int k = 0; k < o.chunk; ++k) {
-        hipError_t e = enqueue_step(P, w, pv, omega, dt, OP_F64, o.gemm_cfg, CHK_PLAIN, false, q);
+        hipError_t e =
+            enqueue_step(P, w, pv, omega, dt, OP_F64, o.gemm_cfg, o.product, CHK_PLAIN, false, q);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -437,7 +465,7 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
       if (e == hipSuccess && o.renorm) e = launch_scale_planes(w.an_r, w.an_i, w.p_a, n, ld, w.st, q);
       if (e == hipSuccess)
         e = enqueue_rhs(P, w, pv, omega, w.an_r, w.an_i, w.p_a, w.ra_r, w.ra_i, OP_F64,
-                        o.gemm_cfg, CHK_JUDGE, q);
+                        o.gemm_cfg, o.product, CHK_JUDGE, q);
       if (e == hipSuccess) e = reset_delta(q);
       return e;
     };
@@ -446,7 +474,8 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
     QPR_HIP(fold_judge(s, true));
     auto chunk_fn = [&](hipStream_t q) -> hipError_t {
       for (int k = 0; k < o.fold_every; ++k) {
-        hipError_t e = enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, CHK_DELTA, true, q);
+        hipError_t e =
+            enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, o.product, CHK_DELTA, true, q);
         if (e != hipSuccess) return e;
       }
       return fold_judge(q, false);
@@ -506,6 +535,8 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   const int xk = op_kind(prec);
   QPR_HIP(launch_state_init(w.st, 0.0, 0, CHK_NONE, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
+  QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
+  QPR_HIP(launch_fill(w.acc_r, 2 * (size_t)P->ld * P->ld * 8, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
   EpiArgs a{};
   a.xr = w.x_r;
@@ -515,8 +546,8 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   a.ysr = w.y1_r;
   a.ysi = w.y1_i;
   a.ps = w.p_1;
-  a.ynr = w.y1_r;
-  a.yni = w.y1_i;
+  a.ynr = w.yn_r;
+  a.yni = w.yn_i;
   a.accr = w.acc_r;
   a.acci = w.acc_i;
   a.outr = w.y2_r;
@@ -524,17 +555,22 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   a.pout = w.p_2;
   a.omega = omega;
   a.cdt = 0.005;
-  a.mode = EPI_S1;  // the stage-1 pass: five plane reads, four plane writes, reduction
-  a.xkind = xk == OP_F64 ? OP_F64 : OP_F32;
+  a.mode = EPI_S2;  // an interior stage: reads Y_s, y_n, acc (+ X), writes acc and Y_{s+1}
+  const bool sparse = cfg == -2 && xk == OP_F64;  // -2: time the sparse fused stage instead
+  a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
   a.lor = xk == OP_F32 ? w.lo_r : nullptr;
   a.loi = xk == OP_F32 ? w.lo_i : nullptr;
   a.slices = xk == OP_BF16X3 ? w.sl : nullptr;
   a.check = CHK_NONE;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   for (auto& e : ev) QPR_HIP(hipEventCreate(&e));
-  for (int r = 0; r < 3; ++r) QPR_HIP(launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s));
+  auto product = [&]() {
+    return sparse ? launch_spmm(pv, w.y1_r, w.y1_i, w.x_r, w.x_i, w.st, 0, s)
+                  : launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s);
+  };
+  for (int r = 0; r < 3; ++r) QPR_HIP(product());
   QPR_HIP(hipEventRecord(ev[0], s));
-  for (int r = 0; r < reps; ++r) QPR_HIP(launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s));
+  for (int r = 0; r < reps; ++r) QPR_HIP(product());
   QPR_HIP(hipEventRecord(ev[1], s));
   for (int r = 0; r < reps; ++r) QPR_HIP(launch_epilogue(pv, a, w, s));
   QPR_HIP(hipEventRecord(ev[2], s));
@@ -552,4 +588,78 @@ extern "C" int32_t qpr_product_configs(int32_t prec) { return gemm_num_cfgs(op_k
 
 extern "C" const char* qpr_product_config_name(int32_t prec, int32_t cfg) {
   return gemm_cfg_name(op_kind(prec), cfg);
+}
+
+extern "C" qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t reps,
+                                   const char* cache_path, int32_t* best_cfg, double* us_out,
+                                   void* ws, size_t wsb, qpr_stream_t stream) {
+  clear_error();
+  Ws w;
+  qpr_status st = check_common(P, 0.5, prec, ws, wsb, &w);
+  if (st != QPR_OK) return st;
+  if (reps < 1) return fail(QPR_E_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int xk = op_kind(prec);
+  const int ncfg = gemm_num_cfgs(xk);
+  const size_t plane = (size_t)P->ld * P->ld;
+  QPR_HIP(launch_state_init(w.st, 0.0, 0, CHK_NONE, s));
+  QPR_HIP(launch_fill(w.y1_r, 2 * plane * 8, s));
+  if (xk == OP_F32) QPR_HIP(launch_fill(w.lo_r, 2 * plane * 4, s));
+  if (xk == OP_BF16X3) QPR_HIP(launch_fill(w.sl, 6 * plane * 2, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QPR_HIP(hipEventCreate(&e0));
+  QPR_HIP(hipEventCreate(&e1));
+  int best = -1;
+  double best_us = 1e300;
+  for (int c = 0; c < ncfg; ++c) {
+    double us = -1.0;
+    // a configuration whose tile does not divide ld cannot run at this size
+    if (gemm_cfg_fits(xk, c, P->ld)) {
+      QPR_HIP(launch_gemm(xk, c, P, w, w.y1_r, w.y1_i, 0, s));
+      QPR_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) QPR_HIP(launch_gemm(xk, c, P, w, w.y1_r, w.y1_i, 0, s));
+      QPR_HIP(hipEventRecord(e1, s));
+      QPR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      us = 1e3 * (double)ms / reps;
+      if (us < best_us) {
+        best_us = us;
+        best = c;
+      }
+    }
+    if (us_out) us_out[c] = us;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (best < 0) return fail(QPR_E_HIP, "no product configuration ran");
+  gemm_set_tuned(xk, P->ld, best);
+  if (best_cfg) *best_cfg = best;
+  if (cache_path && cache_path[0]) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(QPR_E_ARG, "cannot open tuning cache %s", cache_path);
+    fprintf(f, "%d %d %d %.3f %s\n", prec, P->ld, best, best_us, gemm_cfg_name(xk, best));
+    fclose(f);
+  }
+  return QPR_OK;
+}
+
+extern "C" qpr_status qpr_load_tuning(const char* cache_path) {
+  clear_error();
+  if (!cache_path) return fail(QPR_E_ARG, "cache_path must not be NULL");
+  FILE* f = fopen(cache_path, "r");
+  if (!f) return fail(QPR_E_ARG, "cannot open tuning cache %s", cache_path);
+  int prec, ld, cfg;
+  double us;
+  char name[128];
+  int loaded = 0;
+  while (fscanf(f, "%d %d %d %lf %127s", &prec, &ld, &cfg, &us, name) == 5) {
+    const int xk = op_kind(prec);
+    if (cfg >= 0 && cfg < gemm_num_cfgs(xk) && ld > 0 && ld % kPad == 0) {
+      gemm_set_tuned(xk, ld, cfg);  // later lines win
+      ++loaded;
+    }
+  }
+  fclose(f);
+  return loaded > 0 ? QPR_OK : fail(QPR_E_ARG, "no entries in tuning cache %s", cache_path);
 }

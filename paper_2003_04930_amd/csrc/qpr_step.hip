@@ -50,16 +50,18 @@ __device__ __forceinline__ void split3(double v, uint16_t& s1, uint16_t& s2, uin
   s3 = bf16_rn((float)r2);
 }
 
+// Two-level reduction over the `nb` tiles of one system: every tile writes its
+// partial, takes a ticket, and the tile that takes the last ticket sums all
+// partials in index order (deterministic).
 __device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double* partials,
                                                DevState* st, double* red, int* flag,
-                                               double& tot, int& bad) {
+                                               double& tot, int& bad, int tile, int nb) {
   const int tid = threadIdx.x;
-  const int nb = gridDim.x;
   double s = block_sum(my_sum, red, ETHREADS / 64);
   int b = __syncthreads_or(my_bad);
   if (tid == 0) {
-    partials[2 * blockIdx.x] = s;
-    partials[2 * blockIdx.x + 1] = (double)b;
+    partials[2 * tile] = s;
+    partials[2 * tile + 1] = (double)b;
     __threadfence();
     const unsigned int t = atomicAdd(&st->ticket, 1u);
     *flag = (t == (unsigned int)(nb - 1));
@@ -79,10 +81,11 @@ __device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double
   }
 }
 
-template <int XK>
-__global__ void __launch_bounds__(ETHREADS)
-    k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
-  if (st->stop || (a.gate && st->hold)) return;
+template <int XS>
+__device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs& a,
+                                              DevState* __restrict__ st,
+                                              double* __restrict__ partials, int tile,
+                                              int ntiles) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
   __shared__ double gs[TE];
   __shared__ double red[ETHREADS / 64];
@@ -90,7 +93,7 @@ __global__ void __launch_bounds__(ETHREADS)
   const int tid = threadIdx.x, tx = tid & (TE - 1), ty = tid / TE;
   const int n = pv.n, ld = pv.ld;
   const int tiles = ld / TE;
-  const int I = blockIdx.x % tiles, J = blockIdx.x / tiles;
+  const int I = tile % tiles, J = tile / tiles;
   const int a0 = I * TE, b0 = J * TE;
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
@@ -98,7 +101,7 @@ __global__ void __launch_bounds__(ETHREADS)
   for (int m = 0; m < TE / 8; ++m) {
     const int r = ty + 8 * m;
     const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
-    if (XK == OP_F64) {
+    if (XS != XS_DENSE32) {
       Tr[r][tx] = a.xr[o];
       Ti[r][tx] = a.xi[o];
     } else {
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(ETHREADS)
     const bool inside = bin && ar < n;
     if (inside) {
       double A_ab, B_ab;
-      if (XK == OP_F64) {
+      if (XS != XS_DENSE32) {
         A_ab = a.xr[o];
         B_ab = a.xi[o];
       } else {
@@ -211,7 +214,7 @@ __global__ void __launch_bounds__(ETHREADS)
   if (a.mode == EPI_S1 || a.mode == EPI_RHS) {
     double tot;
     int bad;
-    last_block_sum(ssum, sbad, partials, st, red, &flag, tot, bad);
+    last_block_sum(ssum, sbad, partials, st, red, &flag, tot, bad, tile, ntiles);
     if (flag && tid == 0) {
       st->resid2 = tot;
       st->rhs_evals += 1;
@@ -249,6 +252,87 @@ __global__ void __launch_bounds__(ETHREADS)
       }
       st->ticket = 0u;
     }
+  }
+}
+
+template <int XS>
+__global__ void __launch_bounds__(ETHREADS)
+    k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
+  if (st->stop || (a.gate && st->hold)) return;
+  epilogue_tile<XS>(pv, a, st, partials, blockIdx.x, gridDim.x);
+}
+
+// Persistent form for many systems (see k_gemm_k4_batch).  The tiles of one
+// system are counted by that system's own ticket, so its last tile folds its
+// own reduction regardless of which workgroups ran the others.
+template <int XS>
+__global__ void __launch_bounds__(ETHREADS)
+    k_epilogue_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
+                     const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchEpi& e = args[item.x];
+    DevState* st = e.st;
+    if (st->stop || (e.a.gate && st->hold)) continue;
+    const int tiles = e.pv.ld / TE;
+    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y, tiles * tiles);
+    __syncthreads();
+  }
+}
+
+// Sparse commutator product X = H_off Y (FP64) through the CSR of H_off.
+// Workgroup (row a, 128-column chunk): thread t handles plane t / 128 and
+// column c0 + t % 128, summing the neighbour rows of a in CSR order with eight
+// independent loads in flight.  Rows a >= n are left untouched (the epilogue
+// never reads them).
+constexpr int SP_COLS = 128;
+__device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __restrict__ yr,
+                                         const double* __restrict__ yi, double* __restrict__ xr,
+                                         double* __restrict__ xi, int a, int chunk) {
+  const int t = threadIdx.x, c = chunk * SP_COLS + (t & (SP_COLS - 1));
+  if (c >= pv.ld) return;
+  const double* Y = t < SP_COLS ? yr : yi;
+  const int ld = pv.ld;
+  const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
+  int e = e0;
+  for (; e + 8 <= e1; e += 8) {
+    s0 += Y[(size_t)pv.h_idx[e + 0] * ld + c];
+    s1 += Y[(size_t)pv.h_idx[e + 1] * ld + c];
+    s2 += Y[(size_t)pv.h_idx[e + 2] * ld + c];
+    s3 += Y[(size_t)pv.h_idx[e + 3] * ld + c];
+    s4 += Y[(size_t)pv.h_idx[e + 4] * ld + c];
+    s5 += Y[(size_t)pv.h_idx[e + 5] * ld + c];
+    s6 += Y[(size_t)pv.h_idx[e + 6] * ld + c];
+    s7 += Y[(size_t)pv.h_idx[e + 7] * ld + c];
+  }
+  for (; e < e1; ++e) s0 += Y[(size_t)pv.h_idx[e] * ld + c];
+  const double v = (double)pv.hsign * (((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)));
+  (t < SP_COLS ? xr : xi)[(size_t)a * ld + c] = v;
+}
+
+__global__ void __launch_bounds__(2 * SP_COLS)
+    k_spmm(ProbView pv, const double* __restrict__ yr, const double* __restrict__ yi,
+           double* __restrict__ xr, double* __restrict__ xi, const DevState* __restrict__ st,
+           int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
+  spmm_row(pv, yr, yi, xr, xi, blockIdx.x / chunks, blockIdx.x % chunks);
+}
+
+// Persistent form over (system, row * chunks + chunk) items.
+__global__ void __launch_bounds__(2 * SP_COLS)
+    k_spmm_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
+                 const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchEpi& e = args[item.x];
+    if (e.st->stop || (e.a.gate && e.st->hold)) continue;
+    const int chunks = (e.pv.ld + SP_COLS - 1) / SP_COLS;
+    spmm_row(e.pv, e.a.ysr, e.a.ysi, (double*)e.a.xr, (double*)e.a.xi, item.y / chunks,
+             item.y % chunks);
   }
 }
 
@@ -465,18 +549,52 @@ inline int blocks_for(size_t n, int t) { return (int)((n + t - 1) / t); }
 }  // namespace
 
 ProbView view_of(const qpr_problem* P) {
-  return ProbView{P->n, P->ld, P->teleport, P->alpha, P->h_diag, P->d, P->inv_outdeg,
-                  P->dangling, P->in_ptr, P->in_idx};
+  return ProbView{P->n,        P->ld,       P->teleport, P->alpha,
+                  P->h_diag,   P->d,        P->inv_outdeg, P->dangling,
+                  P->in_ptr,   P->in_idx,   P->hdiag == QPR_HDIAG_PAPER ? -1 : 1,
+                  P->h_ptr,    P->h_idx};
 }
 
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s) {
   const int tiles = pv.ld / TE;
   const int grid = tiles * tiles;
   if (grid * 2 > w.max_partials) return hipErrorInvalidValue;
-  if (a.xkind == OP_F64)
-    k_epilogue<OP_F64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  if (a.xkind == XS_DENSE64)
+    k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  else if (a.xkind == XS_DENSE32)
+    k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
+    k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else
-    k_epilogue<OP_F32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
+                       double* xi, const DevState* st, int gate, hipStream_t s) {
+  const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
+  k_spmm<<<pv.n * chunks, 2 * SP_COLS, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+  return hipGetLastError();
+}
+
+int spmm_items_per_system(int n, int ld) { return n * ((ld + SP_COLS - 1) / SP_COLS); }
+
+hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
+                             hipStream_t s) {
+  k_spmm_batch<<<grid, 2 * SP_COLS, 0, s>>>(args, items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* items,
+                                 const int* nitems, int grid, hipStream_t s) {
+  if (xsource == XS_DENSE64)
+    k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else if (xsource == XS_DENSE32)
+    k_epilogue_batch<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else if (xsource == XS_SPARSE64)
+    k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

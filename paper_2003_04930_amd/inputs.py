@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "Graph", "er_digraph", "ba_digraph", "batch_graph", "batch_set",
+    "Graph", "er_digraph", "ba_digraph", "family_graph", "batch_graph", "batch_set",
     "random_density", "random_hermitian", "BATCH_OMEGAS",
 ]
 
@@ -91,18 +91,23 @@ def ba_digraph(n: int, m: int, seed: int = 0, reciprocal: float = 0.1) -> Graph:
     return Graph(n, src, dst, f"ba{n}-m{m}-s{seed}")
 
 
-def batch_graph(k: int) -> Graph:
-    """Graph k of the batched family: seed 1000 + k, N ~ U{50..922}.
+def family_graph(seed: int) -> Graph:
+    """One graph of the mixed family with an explicit seed, N ~ U{50..922}.
 
-    Even k: ER with edge probability 4/(N-1) (mean out-degree 4).
-    Odd k: BA with m ~ U{2..5}, directed as in :func:`ba_digraph`.
+    Even seed: ER with edge probability 4/(N-1) (mean out-degree 4).
+    Odd seed: BA with m ~ U{2..5}, directed as in :func:`ba_digraph`.
     """
-    rng = np.random.default_rng(1000 + k)
+    rng = np.random.default_rng(seed)
     n = int(rng.integers(50, 923))
-    if k % 2 == 0:
-        return er_digraph(n, 4.0 / (n - 1), seed=1000 + k)
+    if seed % 2 == 0:
+        return er_digraph(n, 4.0 / (n - 1), seed=seed)
     m = int(rng.integers(2, 6))
-    return ba_digraph(n, m, seed=1000 + k)
+    return ba_digraph(n, m, seed=seed)
+
+
+def batch_graph(k: int) -> Graph:
+    """Graph k of the batched workload: the family graph with seed 1000 + k."""
+    return family_graph(1000 + k)
 
 
 def batch_set(count: int, first: int = 0):

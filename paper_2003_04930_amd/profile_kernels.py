@@ -1,0 +1,54 @@
+"""Launch one solver kernel repeatedly for hardware-counter passes.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2003_04930_amd.profile_kernels \
+        --n 922 --kernel sparse --reps 20
+
+Runs `reps` launches of the chosen kernel on the benchmark graph (BA m=3 for
+N=922, m=4 otherwise; rho = the FP64 steady state at omega = 0.8 is not
+needed for traffic, a random density matrix is used), then a plain
+device-to-device copy of --copy-mb MiB so the counters can be calibrated
+against a kernel whose traffic is known (copy reads and writes exactly that
+many bytes).
+
+Kernels: sparse (fused sparse RK4 stage), dense (FP64 MFMA product plus the
+dense epilogue), bf16x3 / fp32 (low-precision products plus epilogue).
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=922)
+    ap.add_argument("--kernel", default="sparse", choices=["sparse", "dense", "fp32", "bf16x3"])
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--copy-mb", type=int, default=256)
+    args = ap.parse_args()
+    import torch
+    from paper_2003_04930_amd import inputs, qpr as Q
+
+    g = inputs.ba_digraph(args.n, 3 if args.n <= 1000 else 4, seed=0)
+    P = Q.Problem.from_graph(g)
+    rho = Q.planar(inputs.random_density(args.n, seed=1))
+    prec = {"sparse": "fp64", "dense": "fp64"}.get(args.kernel, args.kernel)
+    cfg = -2 if args.kernel == "sparse" else -1
+    prod_ms, epi_ms = Q.time_kernels(P, 0.8, rho, prec=prec, cfg=cfg, reps=args.reps)
+    nbytes = args.copy_mb << 20
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[profile] n={args.n} kernel={args.kernel} reps={args.reps} "
+          f"product_us={prod_ms * 1e3:.2f} epilogue_us={epi_ms * 1e3:.2f} "
+          f"copy_bytes={nbytes}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "QPR_OK", -1: "QPR_E_ARG", -2: "QPR_E_HIP", -3: "QPR_E_NOT_CO
 TELEPORT = {"paper_f": 0, "uniform": 1}
 HDIAG = {"zero": 0, "paper": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRODUCT = {"auto": 0, "dense": 1, "sparse": 2}
 
 # every symbol include/qpr.h declares
 EXPORTS = (
@@ -33,7 +34,8 @@ EXPORTS = (
     "qpr_rk4_step", "qpr_steady_state", "qpr_rank", "qpr_last_error", "qpr_version",
     "qpr_time_kernels", "qpr_product_configs", "qpr_product_config_name",
     "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
-    "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam",
+    "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam", "qpr_autotune",
+    "qpr_load_tuning", "qpr_batch_workspace_bytes", "qpr_batch_solve",
 )
 
 
@@ -55,7 +57,8 @@ class qpr_problem(C.Structure):
         ("h_diag", C.c_void_p), ("d", C.c_void_p), ("inv_outdeg", C.c_void_p),
         ("dangling", C.c_void_p), ("outdeg", C.c_void_p), ("indeg", C.c_void_p),
         ("in_ptr", C.c_void_p), ("in_idx", C.c_void_p), ("out_ptr", C.c_void_p),
-        ("out_idx", C.c_void_p), ("pagerank", C.c_void_p), ("arena", C.c_void_p),
+        ("out_idx", C.c_void_p), ("pagerank", C.c_void_p), ("h_ptr", C.c_void_p),
+        ("h_idx", C.c_void_p), ("arena", C.c_void_p),
         ("arena_bytes", C.c_size_t),
     ]
 
@@ -81,7 +84,8 @@ class qpr_mpnn_batch(C.Structure):
 
 class qpr_opts(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("use_graph", C.c_int32), ("fold_every", C.c_int32),
-                ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("product", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -102,13 +106,19 @@ def lib():
         "qpr_problem_bytes": (sz, [i32, i64]),
         "qpr_build_google": (i32, [i32, i64, vp, vp, dbl, i32, i32, vp, sz, P, vp]),
         "qpr_workspace_bytes": (sz, [i32, i32]),
-        "qpr_rhs": (i32, [P, dbl, vp, vp, i32, vp, sz, vp]),
-        "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, vp, sz, vp]),
+        "qpr_rhs": (i32, [P, dbl, vp, vp, i32, C.POINTER(qpr_opts), vp, sz, vp]),
+        "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                    C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_rank": (i32, [i32, vp, vp, vp]),
         "qpr_time_kernels": (i32, [P, dbl, i32, i32, i32, vp, C.POINTER(C.c_double), vp, sz, vp]),
         "qpr_product_configs": (i32, [i32]),
+        "qpr_autotune": (i32, [P, i32, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), vp,
+                               sz, vp]),
+        "qpr_load_tuning": (i32, [C.c_char_p]),
+        "qpr_batch_workspace_bytes": (sz, [i32, vp, i32]),
+        "qpr_batch_solve": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
+                                  C.POINTER(qpr_opts), C.POINTER(i32), vp, sz, vp]),
         "qpr_product_config_name": (C.c_char_p, [i32, i32]),
         "qpr_mpnn_param_count": (i32, []),
         "qpr_mpnn_workspace_bytes": (sz, [i32, i32]),
@@ -204,8 +214,10 @@ class Problem:
             return self._view(getattr(self.p, name), self.n, torch.float64)
         if name in ("dangling", "outdeg", "indeg"):
             return self._view(getattr(self.p, name), self.n, torch.int32)
-        if name in ("in_ptr", "out_ptr"):
+        if name in ("in_ptr", "out_ptr", "h_ptr"):
             return self._view(getattr(self.p, name), self.n + 1, torch.int32)
+        if name == "h_idx":
+            return self._view(self.p.h_idx, self.p.nnz_h, torch.int32)
         if name in ("in_idx", "out_idx"):
             return self._view(getattr(self.p, name), self.p.nnz_a, torch.int32)
         raise KeyError(name)
@@ -263,25 +275,34 @@ def _planar_arg(rho, n):
 
 
 # --------------------------------------------------------------- entry points
-def rhs(P: Problem, omega, rho, prec="fp64", out=None):
+def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto"):
+    return qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm),
+                    int(gemm_cfg), PRODUCT[product])
+
+
+def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1):
     torch = _torch()
     rho = _planar_arg(rho, P.n)
     if out is None:
         out = torch.empty_like(rho)
     ws = workspace(P.n, prec)
+    op = make_opts(gemm_cfg=gemm_cfg, product=product)
     _check(lib().qpr_rhs(C.byref(P.p), float(omega), _ptr(rho), _ptr(out), PREC[prec],
-                         C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+                         C.byref(op), C.c_void_p(ws.ptr), ws.nbytes, _stream()))
     return out
 
 
-def rk4_step(P: Problem, omega, dt, nsteps, rho, prec="fp64", diag=False):
+def rk4_step(P: Problem, omega, dt, nsteps, rho, prec="fp64", diag=False, product="auto",
+             gemm_cfg=-1):
     """nsteps RK4 steps in place; returns [res^2, trace, herm, nonfinite] if diag."""
     torch = _torch()
     rho = _planar_arg(rho, P.n)
     ws = workspace(P.n, prec)
     d = torch.zeros(4, dtype=torch.float64, device=rho.device) if diag else None
+    op = make_opts(gemm_cfg=gemm_cfg, product=product)
     _check(lib().qpr_rk4_step(C.byref(P.p), float(omega), float(dt), int(nsteps), _ptr(rho),
-                              PREC[prec], _ptr(d), C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+                              PREC[prec], _ptr(d), C.byref(op), C.c_void_p(ws.ptr), ws.nbytes,
+                              _stream()))
     return d
 
 
@@ -295,7 +316,7 @@ class SolveResult:
 
 def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0=None,
                  want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1,
-                 allow_not_converged=False):
+                 allow_not_converged=False, product="auto"):
     torch = _torch()
     n = P.n
     if rho0 is None:
@@ -305,7 +326,7 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
         rho = _planar_arg(rho0, n).clone()
     rank = torch.empty(n, dtype=torch.int32, device="cuda") if want_rank else None
     st = qpr_stats()
-    op = qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm), int(gemm_cfg))
+    op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product)
     ws = workspace(n, prec)
     status = lib().qpr_steady_state(C.byref(P.p), float(omega), float(dt), float(tol),
                                     int(max_steps), PREC[prec], _ptr(rho), _ptr(rank),
@@ -418,3 +439,69 @@ def mpnn_backward(batch: MpnnBatch, params, p_true):
 def mpnn_adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     _check(lib().qpr_mpnn_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(params.numel()),
                                int(step), float(lr), float(b1), float(b2), float(eps), _stream()))
+
+
+def autotune(P: Problem, prec="fp64", reps=20, cache_path=None):
+    """Time every dense-product tile configuration; returns (best_cfg, {name: us})."""
+    ws = workspace(P.n, prec)
+    L = lib()
+    ncfg = L.qpr_product_configs(PREC[prec])
+    us = (C.c_double * ncfg)()
+    best = C.c_int32(-1)
+    path = cache_path.encode() if cache_path else None
+    _check(L.qpr_autotune(C.byref(P.p), PREC[prec], int(reps), path, C.byref(best), us,
+                          C.c_void_p(ws.ptr), ws.nbytes, _stream()))
+    names = product_configs(prec)
+    return int(best.value), {names[i]: float(us[i]) for i in range(ncfg)}
+
+
+def load_tuning(cache_path):
+    _check(lib().qpr_load_tuning(cache_path.encode()))
+
+
+@dataclass
+class BatchResult:
+    rhos: list
+    ranks: list
+    stats: list
+    status: int
+    tuned_cfg: int
+    seconds: float
+
+
+def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=None,
+                want_rank=True, chunk=32, use_graph=True, gemm_cfg=-1, product="auto",
+                allow_not_converged=False):
+    """Solve [(Problem, omega), ...] together with qpr_batch_solve."""
+    torch = _torch()
+    import time as _time
+    nsys = len(items)
+    ns = (C.c_int32 * nsys)(*[P.n for P, _ in items])
+    nbytes = lib().qpr_batch_workspace_bytes(nsys, ns, PREC[prec])
+    if nbytes == 0:
+        raise QprError(QPR_E_ARG, "invalid batch request")
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + (-buf.data_ptr()) % 256
+    rhos, ranks = [], []
+    for k, (P, _) in enumerate(items):
+        if rho0s is None or rho0s[k] is None:
+            r = torch.zeros((2, P.n, P.n), dtype=torch.float64, device="cuda")
+            r[0].diagonal().fill_(1.0 / P.n)
+        else:
+            r = _planar_arg(rho0s[k], P.n).clone()
+        rhos.append(r)
+        ranks.append(torch.empty(P.n, dtype=torch.int32, device="cuda") if want_rank else None)
+    probs = (C.POINTER(qpr_problem) * nsys)(*[C.pointer(P.p) for P, _ in items])
+    omegas = (C.c_double * nsys)(*[float(w) for _, w in items])
+    rho_ptrs = (C.c_void_p * nsys)(*[r.data_ptr() for r in rhos])
+    rank_ptrs = (C.c_void_p * nsys)(*[(r.data_ptr() if r is not None else None) for r in ranks])
+    stats = (qpr_stats * nsys)()
+    op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product)
+    tuned = C.c_int32(-1)
+    t0 = _time.perf_counter()
+    status = lib().qpr_batch_solve(nsys, probs, omegas, float(dt), float(tol), int(max_steps),
+                                   PREC[prec], rho_ptrs, rank_ptrs, stats, C.byref(op),
+                                   C.byref(tuned), C.c_void_p(base), nbytes, _stream())
+    secs = _time.perf_counter() - t0
+    _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
+    return BatchResult(rhos, ranks, [s.as_dict() for s in stats], status, int(tuned.value), secs)

@@ -106,15 +106,15 @@ def test_build_arena_too_small():
 def test_solver_argument_errors_before_device_work():
     L = _lib()
     st = qpr.qpr_stats()
-    assert L.qpr_rhs(None, 0.5, None, None, 0, None, 0, None) == qpr.QPR_E_ARG
+    assert L.qpr_rhs(None, 0.5, None, None, 0, None, None, 0, None) == qpr.QPR_E_ARG
     assert L.qpr_steady_state(None, 0.5, 0.01, 1e-8, 10, 0, None, None, C.byref(st), None, None,
                               0, None) == qpr.QPR_E_ARG
     assert L.qpr_rank(0, None, None, None) == qpr.QPR_E_ARG
     # a fake problem with bad ld is rejected before any HIP call
     P = qpr.qpr_problem()
     P.n, P.ld = 10, 10
-    assert L.qpr_rk4_step(C.byref(P), 0.5, 0.01, 1, C.c_void_p(256), 0, None, C.c_void_p(256),
-                          1 << 30, None) == qpr.QPR_E_ARG
+    assert L.qpr_rk4_step(C.byref(P), 0.5, 0.01, 1, C.c_void_p(256), 0, None, None,
+                          C.c_void_p(256), 1 << 30, None) == qpr.QPR_E_ARG
     assert "built problem" in L.qpr_last_error().decode()
 
 

@@ -72,30 +72,32 @@ def test_build_matches_oracle(Q, name, teleport, hdiag):
 
 
 # --------------------------------------------------------------------- rhs
+@pytest.mark.parametrize("product", ["dense", "sparse"])
 @pytest.mark.parametrize("name", sorted(GRAPHS))
 @pytest.mark.parametrize("omega", [0.0, 0.35, 0.8, 1.0])
-def test_rhs_fp64_matches_oracle(Q, name, omega):
+def test_rhs_fp64_matches_oracle(Q, name, omega, product):
     g = GRAPHS[name]()
     for teleport, hdiag in (("paper_f", "zero"), ("uniform", "paper")):
         P = Q.Problem.from_graph(g, teleport=teleport, hdiag=hdiag)
         R = oracle_problem(g, teleport=teleport, hdiag=hdiag)
         rho = inputs.random_density(g.n, seed=g.n)
-        got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho)))
+        got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho), product=product))
         want = O.rhs_ref(rho, R.H, R.G, R.d, omega)
         assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
         assert np.array_equal(got, got.conj().T)          # bitwise Hermitian
 
 
 # -------------------------------------------------------------- RK4 steps
+@pytest.mark.parametrize("product", ["dense", "sparse"])
 @pytest.mark.parametrize("name,steps", [("er16", 60), ("er70", 25), ("ba130", 12)])
-def test_rk4_steps_step_locked(Q, name, steps):
+def test_rk4_steps_step_locked(Q, name, steps, product):
     g = GRAPHS[name]()
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
     omega, dt = 0.8, 0.01
     rho0 = inputs.random_density(g.n, seed=5)
     x = Q.planar(rho0)
-    d = Q.rk4_step(P, omega, dt, steps, x, diag=True)
+    d = Q.rk4_step(P, omega, dt, steps, x, diag=True, product=product)
     got = Q.to_complex(x)
     want = O.rk4_ref(rho0, lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega), dt, steps)
     assert np.max(np.abs(got - want)) < 1e-12
@@ -105,14 +107,15 @@ def test_rk4_steps_step_locked(Q, name, steps):
 
 
 # ---------------------------------------------------------- steady state
-def test_steady_state_config1_matches_oracle(Q):
+@pytest.mark.parametrize("product", ["dense", "sparse"])
+def test_steady_state_config1_matches_oracle(Q, product):
     g = GRAPHS["er16"]()
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
     omega, dt, tol = 0.8, 0.01, 1e-10
     f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
     want, nsteps, res = O.steady_ref(np.eye(16) / 16, f, dt, tol, 100000)
-    out = Q.steady_state(P, omega, dt, tol, 100000)
+    out = Q.steady_state(P, omega, dt, tol, 100000, product=product)
     got = Q.to_complex(out.rho)
     assert out.stats["steps"] == nsteps
     assert out.stats["converged"] == 1
@@ -132,14 +135,15 @@ def test_steady_state_graph_and_chunking_do_not_change_result(Q, chunk, use_grap
     assert torch.equal(out.rho, ref.rho)
 
 
-def test_steady_state_ba130_properties_and_oracle(Q):
+@pytest.mark.parametrize("product", ["dense", "sparse"])
+def test_steady_state_ba130_properties_and_oracle(Q, product):
     g = GRAPHS["ba130"]()
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
     omega, dt, tol = 0.6, 0.01, 1e-9
     f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
     want, nsteps, _ = O.steady_ref(np.eye(g.n) / g.n, f, dt, tol, 100000)
-    out = Q.steady_state(P, omega, dt, tol, 100000)
+    out = Q.steady_state(P, omega, dt, tol, 100000, product=product)
     got = Q.to_complex(out.rho)
     assert out.stats["steps"] == nsteps
     assert np.max(np.abs(got - want)) < 1e-10
@@ -194,9 +198,15 @@ def test_rhs_full_size(Q, n, m):
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
     rho = inputs.random_density(n, seed=1)
-    got = Q.to_complex(Q.rhs(P, 0.8, Q.planar(rho)))
     want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.8)
-    assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+    for product in ("dense", "sparse"):
+        got = Q.to_complex(Q.rhs(P, 0.8, Q.planar(rho), product=product))
+        assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+    # the H_off pattern the sparse product gathers through
+    hp = P.vector("h_ptr").cpu().numpy()
+    hi = P.vector("h_idx").cpu().numpy()
+    for a in (0, 1, n // 2, n - 1):
+        assert list(hi[hp[a]:hp[a + 1]]) == list(np.nonzero(R.H[a] - np.diag(np.diag(R.H))[a])[0])
 
 
 def test_steady_state_n922_properties(Q):
