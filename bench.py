@@ -8,10 +8,10 @@ omega = 0.2, 0.5, 0.8, and ranked.  `value` is the mean time-to-steady-state
 per solve in seconds (inputs resident in HBM; host readback of the device
 flag once per chunk is part of it).
 
-Also reported (same graph, same omegas): the mixed-precision solves (BF16x3
-and FP32 products with FP64 judge), the roofline of the dominant kernel (the
-FP64 commutator product, timed with HIP events on the solve's stream), and
-the CPU oracle on a bounded sample of the same workload.
+Also reported (same graph, same omegas): the dense FP64 MFMA solve, the
+mixed-precision solves (BF16x3 and FP32 MFMA products with FP64 judge), the
+roofline of the dominant kernel of the timed path (timed with HIP events on
+the solve's stream), and the CPU oracle on a bounded sample of the workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mixed]
 """
@@ -82,6 +82,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=0,
+                    help="also time qpr_batch_solve on this many family graphs x 5 omegas")
+    ap.add_argument("--precision-n", type=int, default=0,
+                    help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
+    ap.add_argument("--warm", default=None, help="warm-start weights (.npy) to time as well")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -120,25 +125,33 @@ def main():
     log(f"fp64: {value:.3f} s/solve, steps {steps}")
 
     # Kernels of the timed path, timed with HIP events on the solve's stream.
-    # The auto product at this density is the sparse fused stage (one launch
-    # per stage); the dense MFMA product and its epilogue are timed too.
+    # At this density the product is the sparse one (CSR gathers, k_spmm);
+    # each stage is k_spmm + the fused epilogue.  The dense MFMA product is
+    # timed too.
     rho_ss = results[-1].rho
     sparse = P.p.nnz_h < 0.05 * N * N
-    _, sp_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", cfg=-2, reps=200)
-    gemm_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
+    sp_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", cfg=-2, reps=200)
+    gemm_ms, _ = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
     ld = P.ld
-    stage_bytes = 16.0 * N * N * 5             # interior stage: read Y_s, y_n, acc; write acc, Y_s+1
+    # algorithmic bytes per launch (interior stage):
+    #   epilogue: X read once (16 B/elem), Y_s, y_n, acc read on the upper
+    #   triangle (3 x 8 B/elem), acc written there (8), Y_s+1 written in full (16)
+    epi_bytes = 64.0 * N * N
+    #   sparse product: each gathered row of Y read once from HBM (16 B/elem),
+    #   X written (16 B/elem); the nnz_H-fold re-reads hit the caches
+    sp_bytes = 32.0 * N * N
     flops = 4.0 * N ** 3                       # dense product: two real N x N x N products
     gemm_tf = flops / (gemm_ms * 1e-3) / 1e12
-    epi_gbs = (stage_bytes + 32.0 * N * N) / (epi_ms * 1e-3) / 1e9   # + X_ab, X_ba reads
-    sp_gbs = stage_bytes / (sp_ms * 1e-3) / 1e9
-    log(f"sparse stage {sp_ms * 1e3:.1f} us ({sp_gbs:.0f} GB/s algorithmic); dense product "
-        f"{gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s), dense epilogue {epi_ms * 1e3:.1f} us")
+    epi_gbs = epi_bytes / (epi_ms * 1e-3) / 1e9
+    sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9
+    log(f"stage: spmm {sp_ms * 1e3:.1f} us ({sp_gbs:.0f} GB/s), epilogue {epi_ms * 1e3:.1f} us "
+        f"({epi_gbs:.0f} GB/s); dense product {gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s)")
     if sparse:
-        roofline = {"bound": "hbm", "achieved": sp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": sp_gbs / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "k_epilogue<XS_SPARSE64> (fused sparse RK4 stage)",
-                    "bytes_per_launch": stage_bytes, "us_per_launch": sp_ms * 1e3}
+        dom = ("k_epilogue (fused RHS + RK4 stage)", epi_gbs, epi_bytes, epi_ms) \
+            if epi_ms >= sp_ms else ("k_spmm (sparse commutator product)", sp_gbs, sp_bytes, sp_ms)
+        roofline = {"bound": "hbm", "achieved": dom[1], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": dom[1] / HBM_PEAK_GBS, "traffic": None, "kernel": dom[0],
+                    "bytes_per_launch": dom[2], "us_per_launch": dom[3] * 1e3}
     else:
         roofline = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": gemm_tf / FP64_PEAK_TFLOPS, "traffic": None,
@@ -150,11 +163,25 @@ def main():
              "dense_product": {"us": gemm_ms * 1e3, "achieved_TFs": gemm_tf,
                                "peak_TFs": FP64_PEAK_TFLOPS, "frac": gemm_tf / FP64_PEAK_TFLOPS,
                                "flops_per_launch": flops},
-             "dense_epilogue": {"us": epi_ms * 1e3, "achieved_GBs": epi_gbs,
-                                "frac": epi_gbs / HBM_PEAK_GBS},
-             "sparse_stage": {"us": sp_ms * 1e3, "achieved_GBs": sp_gbs,
-                              "frac": sp_gbs / HBM_PEAK_GBS},
+             "epilogue": {"us": epi_ms * 1e3, "achieved_GBs": epi_gbs,
+                          "frac": epi_gbs / HBM_PEAK_GBS, "bytes_per_launch": epi_bytes},
+             "spmm": {"us": sp_ms * 1e3, "achieved_GBs": sp_gbs,
+                      "frac": sp_gbs / HBM_PEAK_GBS, "bytes_per_launch": sp_bytes},
              "nnz_h": int(P.p.nnz_h), "ld": ld}
+
+    # the paper's own integrator: adaptive Fehlberg 4(5), FP64, same tolerance
+    t0f = time.perf_counter()
+    rf = [Q.steady_state(P, w, DT, TOL, 400000, integrator="rkf45") for w in OMEGAS]
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0f) / len(OMEGAS)
+    errf = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rf, results))
+    extra["fp64_rkf45"] = {"seconds_per_solve": tf,
+                           "accepted_steps": [r.stats["steps"] for r in rf],
+                           "rejected_steps": [r.stats["rejected"] for r in rf],
+                           "last_step": [r.stats["last_step"] for r in rf],
+                           "max_abs_drho_vs_rk4": errf, "speedup_vs_rk4": value / tf}
+    log(f"fp64 rkf45: {tf:.3f} s/solve, accepted {[r.stats['steps'] for r in rf]}, "
+        f"rejected {[r.stats['rejected'] for r in rf]}, max|drho| vs RK4 {errf:.1e}")
 
     if not args.no_dense:
         t0d = time.perf_counter()
@@ -184,6 +211,65 @@ def main():
                 "product_frac": flops / (pm * 1e-3) / 1e12 / peak,
                 "speedup_vs_fp64": value / tm}
             log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
+
+    if args.warm:
+        from paper_2003_04930_amd import warmstart as W
+        params = W.load(args.warm)
+        for prec in ("fp64", "fp32"):
+            t0w = time.perf_counter()
+            rw = solve_all(Q, P, prec, rho0_fn=lambda w: W.warm_rho0(P, w, params))
+            torch.cuda.synchronize()
+            tw = (time.perf_counter() - t0w) / len(OMEGAS)
+            err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rw, results))
+            extra[f"warm_{prec}"] = {"seconds_per_solve": tw,
+                                     "rk4_steps": [r.stats["steps"] for r in rw],
+                                     "max_abs_drho_vs_cold_fp64": err,
+                                     "speedup_vs_cold_fp64": value / tw}
+            log(f"warm start {prec}: {tw:.3f} s/solve, steps {[r.stats['steps'] for r in rw]}")
+
+    if args.batch_graphs:
+        items = []
+        for k in range(args.batch_graphs):
+            Pk = Q.Problem.from_graph(inputs.batch_graph(k))
+            items += [(Pk, w) for w in inputs.BATCH_OMEGAS]
+        for prec in ("fp64", "fp32"):
+            rb = Q.batch_solve(items, prec=prec, tol=TOL, want_rank=True)
+            st = [x["steps"] for x in rb.stats]
+            extra[f"batch_{prec}"] = {
+                "systems": len(items), "seconds": rb.seconds,
+                "solves_per_s": len(items) / rb.seconds, "tuned_cfg": rb.tuned_cfg,
+                "steps_min_mean_max": [min(st), float(np.mean(st)), max(st)],
+                "sum_n2": int(sum(Pk.n ** 2 for Pk, _ in items))}
+            log(f"batch {prec}: {len(items)} systems in {rb.seconds:.2f} s "
+                f"({len(items) / rb.seconds:.2f} solves/s)")
+
+    if args.precision_n:
+        nP = args.precision_n
+        Pn = Q.Problem.from_graph(inputs.ba_digraph(nP, 4, seed=0))
+        ref = Q.steady_state(Pn, 0.8, DT, TOL, 400000)
+        row = {"fp64_sparse": {"seconds": ref.stats["seconds"], "rk4_steps": ref.stats["steps"]}}
+        p_ref = ref.rho[0].diagonal().double()
+        for prec in ("fp32", "bf16x3"):
+            r = Q.steady_state(Pn, 0.8, DT, TOL, 400000, prec=prec)
+            err = float((r.rho - ref.rho).abs().max())
+            # ranking agreement on pairs whose gap exceeds 2 max|drho| (tie classes below)
+            p = p_ref.cpu().numpy()
+            pos = np.empty(nP, dtype=np.int64)
+            pos[r.rank.cpu().numpy()] = np.arange(nP)
+            tau = 2 * err
+            order = np.argsort(-p, kind="stable")
+            bad = 0
+            for i in range(nP - 1):
+                a_, b_ = order[i], order[i + 1]
+                if p[a_] - p[b_] > tau and pos[a_] > pos[b_]:
+                    bad += 1
+            ties = int(np.sum(np.diff(np.sort(p)) <= tau))
+            row[prec] = {"seconds": r.stats["seconds"], "rk4_steps": r.stats["steps"],
+                         "folds": r.stats["folds"], "max_abs_drho_vs_fp64": err,
+                         "adjacent_order_violations_beyond_tau": bad, "tie_gaps_within_tau": ties}
+            log(f"precision n={nP} {prec}: {r.stats['seconds']:.2f} s, max|drho| {err:.2e}, "
+                f"order violations {bad}, tie gaps {ties}")
+        extra[f"precision_n{nP}"] = row
 
     cpu = None
     if not args.no_cpu:

@@ -89,6 +89,7 @@ typedef struct {
   int32_t teleport;     /* qpr_teleport                                       */
   int32_t hdiag;        /* qpr_hdiag                                          */
   double h_lo, h_hi;    /* Gershgorin interval containing the spectrum of H   */
+  double h_norm;        /* spectral radius of H, power-iteration estimate     */
   int32_t pagerank_iters; /* power iterations used for `pagerank`             */
   int32_t reserved;
   /* device arrays inside the arena */
@@ -126,6 +127,8 @@ typedef struct {
   double seconds;         /* host wall time of the call                       */
   int32_t converged;      /* 1 if residual < tol                              */
   int32_t status;         /* qpr_status of the call                           */
+  int64_t rejected;       /* adaptive integration: rejected step attempts     */
+  double last_step;       /* adaptive integration: step size at the end       */
 } qpr_stats;
 
 /* Solver options; pass NULL for the defaults in brackets. */
@@ -136,8 +139,18 @@ typedef struct {
   int32_t renorm;     /* mixed precision: divide by the trace at folds [1]    */
   int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1]  */
   int32_t product;    /* qpr_product [QPR_PRODUCT_AUTO]                       */
-  int32_t reserved[2];
+  int32_t integrator; /* qpr_integrator [QPR_RK4]                             */
+  int32_t reserved;
+  double step_tol;    /* RKF45: local error tolerance per unit step [1e-4]    */
+  double dt_max;      /* RKF45: step cap; 0 = from the spectral radius of H [0] */
 } qpr_opts;
+
+/* Time integrator of qpr_steady_state. */
+typedef enum {
+  QPR_RK4 = 0,   /* classical RK4, fixed step dt (Supplementary Note 2)       */
+  QPR_RKF45 = 1  /* Fehlberg 4(5) with the step control of Eq. (S13): dt is the
+                    first step; the two 4101 denominators read as 4104; FP64 */
+} qpr_integrator;
 
 /* How the commutator product X = H_off rho is formed. */
 typedef enum {
@@ -345,6 +358,14 @@ qpr_status qpr_load_tuning(const char* cache_path);
 /* Number of product tile configurations at precision prec, and their names. */
 int32_t qpr_product_configs(int32_t prec);
 const char* qpr_product_config_name(int32_t prec, int32_t cfg);
+
+/*
+ * Hub classes of the results section: counts[0] = #{i : p_i > c/N} (main
+ * hubs), counts[1] = #{i : 1/N < p_i <= c/N} (secondary hubs); the paper
+ * uses c = 10.  p device n doubles, counts device int32[2].  Asynchronous.
+ */
+qpr_status qpr_hub_counts(int32_t n, const double* p, double c, int32_t* counts,
+                          qpr_stream_t stream);
 
 /* Message for this thread's last non-OK status ("" if none). */
 const char* qpr_last_error(void);

@@ -306,14 +306,15 @@ FEHLBERG = {
 
 
 def rkf45_ref(y0, f, h0, tol_step, t_end=None, tol_ss=None, max_steps=100000,
-              h_max=None):
+              h_max=None, raise_on_limit=True):
     """Adaptive Fehlberg 4(5) integration (Supplementary Note 2).
 
     Step factor s = (tol_step * h / (2 |z - y|))^(1/4) (Eq. (S13)); |.| read as
     the max-abs norm.  A step is accepted when |z - y| <= tol_step * h and the
     fourth-order y is kept.  Stops at t_end, or when tol_ss is given at the
     first accepted state with ||f(y)||_F < tol_ss.  Returns (y, t, accepted,
-    rejected).
+    rejected); after max_steps attempts it raises, or with raise_on_limit=False
+    returns the state reached.
     """
     y = np.array(y0, dtype=np.complex128)
     t, h = 0.0, h0
@@ -345,4 +346,6 @@ def rkf45_ref(y0, f, h0, tol_step, t_end=None, tol_ss=None, max_steps=100000,
         h = h * min(4.0, max(0.1, s_fac))
         if h_max is not None:
             h = min(h, h_max)
-    raise RuntimeError("rkf45: step limit reached")
+    if raise_on_limit:
+        raise RuntimeError("rkf45: step limit reached")
+    return y, t, acc, rej

@@ -108,7 +108,7 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
     L.sys.push_back(si);
     const size_t tg = (size_t)(si.ld / gtile) * (si.ld / gtile);
     L.max_g += std::max(tg, (size_t)(si.ld / 32) * (si.ld / 32));  // any batch tile size
-    L.max_e += (size_t)(si.ld / TE) * (si.ld / TE);
+    L.max_e += (size_t)epilogue_items_per_system(si.ld);
     L.max_f += (size_t)(si.ld / TE);
     L.max_s += (size_t)spmm_items_per_system(si.n, si.ld);
   }
@@ -324,7 +324,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     for (int k : order) {
       if (!active[k]) continue;
       const int ld = pad_n(ns[k]);
-      const int tg = (ld / gtile) * (ld / gtile), te = (ld / TE) * (ld / TE);
+      const int tg = (ld / gtile) * (ld / gtile), te = epilogue_items_per_system(ld);
       for (int t = 0; t < tg; ++t) ig.push_back(make_int2(k, t));
       for (int t = 0; t < te; ++t) ie.push_back(make_int2(k, t));
       for (int t = 0; t < ld / TE; ++t) iff.push_back(make_int2(k, t));

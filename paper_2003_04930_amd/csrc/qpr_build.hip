@@ -19,7 +19,7 @@ namespace {
 struct Summary {          // device -> host after the build
   long long nnz_a, nnz_h;
   int self_loops, dangling, pr_iters, pad;
-  double h_lo, h_hi;
+  double h_lo, h_hi, h_norm;
 };
 
 struct ArenaLayout {
@@ -277,6 +277,46 @@ __global__ void __launch_bounds__(1024) k_pagerank(GainView gv, double* p, doubl
   (void)sums;
 }
 
+// Spectral radius estimate of H = diag(h) + H_off by power iteration (one
+// workgroup, fixed start vector, `iters` products through the CSR of H_off).
+// The Rayleigh quotients increase towards the spectral radius; the largest
+// one seen is kept.
+__global__ void __launch_bounds__(1024) k_spectral(int n, const int* __restrict__ h_ptr,
+                                                   const int* __restrict__ h_idx, int hsign,
+                                                   const double* __restrict__ hd, double* x,
+                                                   double* y, int iters, Summary* sm) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double nrm2 = 0.0;
+  for (int i = t; i < n; i += 1024) {
+    const double v = 1.0 + 0.5 * sin(0.7 * (double)i);
+    x[i] = v;
+    nrm2 += v * v;
+  }
+  nrm2 = block_sum_1024(nrm2, red);
+  double best = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    const double inv = 1.0 / sqrt(nrm2);
+    double dot = 0.0, yy = 0.0;
+    for (int i = t; i < n; i += 1024) {
+      double acc = hd[i] * x[i];
+      for (int e = h_ptr[i]; e < h_ptr[i + 1]; ++e) acc += (double)hsign * x[h_idx[e]];
+      acc *= inv;
+      y[i] = acc;
+      dot += acc * x[i] * inv;
+      yy += acc * acc;
+    }
+    dot = block_sum_1024(dot, red);   // Rayleigh quotient of x / |x|
+    yy = block_sum_1024(yy, red);
+    best = fmax(best, fabs(dot));
+    for (int i = t; i < n; i += 1024) x[i] = y[i];
+    __syncthreads();
+    nrm2 = yy;
+    if (!(nrm2 > 0.0)) break;
+  }
+  if (t == 0) sm->h_norm = best;
+}
+
 }  // namespace
 
 }  // namespace qpr
@@ -372,6 +412,11 @@ extern "C" qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t
   GainView gv{n, teleport, alpha, P.inv_outdeg, P.dangling, P.in_ptr, P.in_idx};
   k_pagerank<<<1, 1024, 0, s>>>(gv, P.pagerank, (double*)(base + L.pr_tmp), 4000, sm);
   QPR_HIP(hipGetLastError());
+  // scratch for the power iteration: the FP64 H plane is not touched, the
+  // byte adjacency (no longer needed) is reused
+  k_spectral<<<1, 1024, 0, s>>>(n, P.h_ptr, P.h_idx, hsign, P.h_diag, (double*)A8,
+                                (double*)A8 + ld, 300, sm);
+  QPR_HIP(hipGetLastError());
   Summary h{};
   QPR_HIP(hipMemcpyAsync(&h, sm, sizeof(Summary), hipMemcpyDeviceToHost, s));
   QPR_HIP(hipStreamSynchronize(s));
@@ -381,6 +426,7 @@ extern "C" qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t
   P.n_dangling = h.dangling;
   P.h_lo = h.h_lo;
   P.h_hi = h.h_hi;
+  P.h_norm = h.h_norm;
   P.pagerank_iters = h.pr_iters;
   *out = P;
   return QPR_OK;

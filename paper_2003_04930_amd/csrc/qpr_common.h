@@ -47,6 +47,16 @@ struct DevState {
   double judge2;        // mixed precision: latest FP64 ||L(rho_a)||_F^2
   long long folds;      // mixed precision: FP64 judge evaluations
   double aux[8];        // final-state diagnostics (trace, herm, min diag, ...)
+  // adaptive Fehlberg 4(5) integration
+  double h;             // current step size
+  double h_max;         // cap on the step size
+  double tol_step;      // local error tolerance per unit step
+  double t;             // integrated time of the accepted state
+  double err;           // latest max |z - y|
+  long long accepted;   // accepted steps
+  long long rejected;   // rejected steps
+  int accept;           // the latest attempt was accepted
+  int pad1;
 };
 
 // Values of EpiArgs::check
@@ -54,7 +64,8 @@ enum CheckMode {
   CHK_NONE = 0,   // record ||k||^2 only
   CHK_PLAIN = 1,  // stage 1 of the FP64 solve: converge / count steps
   CHK_DELTA = 2,  // stage 1 of a low-precision delta step: hold when the estimate meets tol
-  CHK_JUDGE = 3   // FP64 residual of the anchor: converge, or release the hold
+  CHK_JUDGE = 3,  // FP64 residual of the anchor: converge, or release the hold
+  CHK_RKF = 4     // stage 1 of a Fehlberg attempt: converge / count attempts
 };
 
 // Workspace carved from the caller's buffer.  Planes are ld*ld.
@@ -71,6 +82,8 @@ struct Ws {
   float *lo_r = nullptr, *lo_i = nullptr;    // FP32 operand copy (QPR_FP32)
   uint16_t* sl = nullptr;                    // bf16 slices: [plane][slice][ld*ld]
   double *p_n = nullptr, *p_1 = nullptr, *p_2 = nullptr, *p_a = nullptr; // diagonals (n)
+  double *k_r[5] = {}, *k_i[5] = {};         // Fehlberg stage derivatives (FP64 only)
+  double *cand_r = nullptr, *cand_i = nullptr, *p_c = nullptr;  // Fehlberg candidate state
   double* partials = nullptr;                // per-workgroup partial sums
   int max_partials = 0;
   DevState* st = nullptr;
@@ -94,7 +107,9 @@ struct ProbView {
 };
 ProbView view_of(const qpr_problem* P);
 
-enum EpiMode { EPI_RHS = 0, EPI_S1 = 1, EPI_S2 = 2, EPI_S3 = 3, EPI_S4 = 4 };
+// Epilogue modes: the right-hand side alone, the four classical RK4 stages,
+// and the six Fehlberg 4(5) stages (EPI_F1 + s - 1 for stage s).
+enum EpiMode { EPI_RHS = 0, EPI_S1 = 1, EPI_S2 = 2, EPI_S3 = 3, EPI_S4 = 4, EPI_F1 = 11 };
 
 // Which buffer kind the epilogue reads X from and what lowp copy it writes.
 enum OpKind { OP_F64 = 0, OP_F32 = 1, OP_BF16X3 = 2 };
@@ -122,6 +137,11 @@ struct EpiArgs {
   int mode, xkind;             // xkind: XSource
   int check;                  // CheckMode
   int gate;                   // 1: also return when DevState::hold is set
+  // Fehlberg stages (mode EPI_F1 .. EPI_F1 + 5)
+  const double *kr[5], *ki[5];  // K_1 .. K_5 (upper triangle)
+  double *kwr, *kwi;            // where this stage stores its K (stages 1..5)
+  double cf[6];                 // stage s < 6: a_{s+1, 1..s}; stage 6: b4
+  double ce[6];                 // stage 6: b5 - b4
 };
 
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w,
@@ -136,13 +156,19 @@ hipError_t launch_to_lowp(int kind, const double* r, const double* i, int n,
                           int ld, const Ws& w, hipStream_t s);
 hipError_t launch_state_init(DevState* st, double tol, long long max_steps,
                              int check, hipStream_t s);
+hipError_t launch_state_rkf(DevState* st, double h0, double h_max, double tol_step,
+                            hipStream_t s);
 hipError_t launch_state_stats(const double* r, const double* i, const double* p,
                               int n, int ld, const Ws& w, hipStream_t s);
 hipError_t launch_rank(int n, const double* p, int* order, hipStream_t s);
+hipError_t launch_hubs(int n, const double* p, double c, int* out, hipStream_t s);
 hipError_t launch_axpy_planes(double* yr, double* yi, const double* xr,
                               const double* xi, double a, int n, int ld,
                               double* p, const DevState* st, hipStream_t s);
 hipError_t launch_trace(const double* p, int n, DevState* st, hipStream_t s);
+hipError_t launch_rkf_commit(double* yr, double* yi, double* p, const double* cr,
+                             const double* ci, const double* pc, int n, int ld,
+                             const DevState* st, hipStream_t s);
 hipError_t launch_fill(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_scale_planes(double* r, double* i, double* p, int n, int ld,
                                const DevState* st, hipStream_t s);
@@ -171,6 +197,7 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
                        double* xi, const DevState* st, int gate, hipStream_t s);
 int spmm_items_per_system(int n, int ld);
+int epilogue_items_per_system(int ld);
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
                              hipStream_t s);
 

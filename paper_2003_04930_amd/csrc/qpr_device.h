@@ -53,6 +53,19 @@ __device__ __forceinline__ double block_sum(double v, double* red, int nw) {
   return s;
 }
 
+// Max over a block of `nw` waves; every thread gets the result.
+__device__ __forceinline__ double block_max(double v, double* red, int nw) {
+  const int t = threadIdx.x;
+  v = wave_max_d(v);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < nw; ++w) s = fmax(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
 // What the gain (G p)_a needs: G itself is never stored.
 struct GainView {
   int n, teleport;
@@ -62,6 +75,24 @@ struct GainView {
   const int* in_ptr;
   const int* in_idx;
 };
+
+// The teleport and dangling part of (G p)_a, given s = sum over in-links j of
+// p_j / outDeg(j).
+__device__ __forceinline__ double gain_finish(const GainView& g, int a, const double* p,
+                                              double P, double D, double s) {
+  double tel, dang;
+  if (g.teleport == QPR_TELEPORT_PAPER_F) {
+    const double inv = 1.0 / (double)(g.n - 1);
+    const double pa = p[a];
+    tel = (P - pa) * inv;
+    dang = (D - (g.dangling[a] ? pa : 0.0)) * inv;
+  } else {
+    const double inv = 1.0 / (double)g.n;
+    tel = P * inv;
+    dang = D * inv;
+  }
+  return g.alpha * (s + dang) + (1.0 - g.alpha) * tel;
+}
 
 // (G p)_a for G = alpha S + (1 - alpha) T with dangling columns set to T.
 //   P = sum_j p_j,  D = sum over dangling j of p_j.

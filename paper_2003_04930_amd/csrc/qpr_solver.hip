@@ -3,6 +3,7 @@
 // product judged in FP64).
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -54,7 +55,7 @@ static int op_kind(int prec) {
 // ---------------------------------------------------------------- workspace
 namespace {
 struct WsLayout {
-  size_t yn, y1, y2, acc, x, ra, an, xf, lo, sl, pv, partials, st, scal, total;
+  size_t yn, y1, y2, acc, x, ra, an, xf, lo, sl, pv, kf, cand, pc, partials, st, scal, total;
   int max_partials;
 };
 
@@ -77,8 +78,13 @@ WsLayout ws_layout(int n, int prec) {
     if (prec == QPR_BF16X3) L.sl = take(6 * ph);
   }
   L.pv = take(4 * ld * 8);
+  if (prec == QPR_FP64) {  // Fehlberg: K_1..K_5, candidate state and its diagonal
+    L.kf = take(10 * pd);
+    L.cand = take(2 * pd);
+    L.pc = take(ld * 8);
+  }
   const size_t tiles = (ld / 32) * (ld / 32);
-  L.max_partials = (int)std::max<size_t>(2 * tiles, 4 * 1024);
+  L.max_partials = (int)std::max<size_t>(3 * tiles, 4 * 1024);
   L.partials = take((size_t)L.max_partials * 8);
   L.st = take(sizeof(DevState));
   L.scal = take(16 * 8);
@@ -126,6 +132,16 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w) {
   w->p_1 = pv + ld;
   w->p_2 = pv + 2 * ld;
   w->p_a = pv + 3 * ld;
+  if (prec == QPR_FP64) {
+    double* kf = (double*)(b + L.kf);
+    for (int j = 0; j < 5; ++j) {
+      w->k_r[j] = kf + (2 * j) * pl;
+      w->k_i[j] = kf + (2 * j + 1) * pl;
+    }
+    w->cand_r = (double*)(b + L.cand);
+    w->cand_i = w->cand_r + pl;
+    w->p_c = (double*)(b + L.pc);
+  }
   w->partials = (double*)(b + L.partials);
   w->max_partials = L.max_partials;
   w->st = (DevState*)(b + L.st);
@@ -254,6 +270,100 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
   return launch_epilogue(pv, a, w, s);
 }
 
+// Fehlberg 4(5) tableau (Supplementary Note 2, Eq. (S10)-(S12)), the two
+// 4101 denominators read as 4104 (the order conditions require it).
+static const double kFa[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 4, 0, 0, 0, 0},
+    {3.0 / 32, 9.0 / 32, 0, 0, 0},
+    {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0},
+    {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0},
+    {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40},
+};
+static const double kFb4[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
+static const double kFb5[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
+
+// Stability cap for the Fehlberg fourth-order solution.  Its stability
+// polynomial is R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 + z^5/104 (b4 A^k 1
+// from the tableau above); because of the z^5/104 term |R(i y)| > 1 for every
+// y != 0 on the imaginary axis, so steps are only stable for modes with
+// enough damping.  The Liouvillian's fast modes are coherences between
+// eigenstates of H, eigenvalues ~ -omega + i beta with
+// |beta| <= (1 - omega) 2 rho(H); the classical part lies within radius
+// 2 omega.  The cap is the largest h (bisection) with |R(h z)| <= 1 on that
+// set, taking half the dephasing rate as the damping, times 0.9.
+static double rkf_step_cap(double omega, double rho_h) {
+  const double bmax = (1.0 - omega) * 2.0 * 1.02 * rho_h;
+  const double gamma = 0.5 * omega;
+  auto R = [](std::complex<double> z) {
+    return 1.0 + z * (1.0 + z * (0.5 + z * (1.0 / 6 + z * (1.0 / 24 + z / 104.0))));
+  };
+  auto ok = [&](double h) {
+    if (std::abs(R(std::complex<double>(-2.0 * omega * h, 0.0))) > 1.0) return false;
+    for (int k = 0; k <= 2000; ++k) {
+      const double b = bmax * k / 2000.0;
+      if (std::abs(R(std::complex<double>(-gamma * h, b * h))) > 1.0) return false;
+    }
+    return true;
+  };
+  double lo = 0.0, hi = 4.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (ok(mid) ? lo : hi) = mid;
+  }
+  return 0.9 * lo;
+}
+
+// One Fehlberg attempt on y = (yn, p_n): six stages (product + epilogue),
+// then the commit of the candidate if the step control accepted it.
+static hipError_t enqueue_rkf_attempt(const qpr_problem* P, const Ws& w, const ProbView& pv,
+                                      double omega, int cfg, int product, hipStream_t s) {
+  const bool sparse = use_sparse(P, product, OP_F64);
+  double* in_r[6] = {w.yn_r, w.y1_r, w.y2_r, w.y1_r, w.y2_r, w.y1_r};
+  double* in_i[6] = {w.yn_i, w.y1_i, w.y2_i, w.y1_i, w.y2_i, w.y1_i};
+  double* in_p[6] = {w.p_n, w.p_1, w.p_2, w.p_1, w.p_2, w.p_1};
+  for (int st = 0; st < 6; ++st) {
+    hipError_t e = sparse ? launch_spmm(pv, in_r[st], in_i[st], w.x_r, w.x_i, w.st, 0, s)
+                          : launch_gemm(OP_F64, cfg, P, w, in_r[st], in_i[st], 0, s);
+    if (e != hipSuccess) return e;
+    EpiArgs a{};
+    a.xr = w.x_r;
+    a.xi = w.x_i;
+    a.ysr = in_r[st];
+    a.ysi = in_i[st];
+    a.ps = in_p[st];
+    a.ynr = w.yn_r;
+    a.yni = w.yn_i;
+    a.omega = omega;
+    a.mode = EPI_F1 + st;
+    a.xkind = sparse ? XS_SPARSE64 : XS_DENSE64;
+    a.check = st == 0 ? CHK_RKF : CHK_NONE;
+    for (int j = 0; j < 5; ++j) {
+      a.kr[j] = w.k_r[j];
+      a.ki[j] = w.k_i[j];
+    }
+    if (st < 5) {
+      a.kwr = w.k_r[st];
+      a.kwi = w.k_i[st];
+      a.outr = in_r[st + 1];
+      a.outi = in_i[st + 1];
+      a.pout = in_p[st + 1];
+      for (int j = 0; j <= st; ++j) a.cf[j] = kFa[st + 1][j];
+    } else {
+      a.outr = w.cand_r;
+      a.outi = w.cand_i;
+      a.pout = w.p_c;
+      for (int j = 0; j < 6; ++j) {
+        a.cf[j] = kFb4[j];
+        a.ce[j] = kFb5[j] - kFb4[j];
+      }
+    }
+    e = launch_epilogue(pv, a, w, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_rkf_commit(w.yn_r, w.yn_i, w.p_n, w.cand_r, w.cand_i, w.p_c, P->n, P->ld, w.st, s);
+}
+
 }  // namespace qpr
 
 using namespace qpr;
@@ -274,6 +384,9 @@ static qpr_opts default_opts() {
   o.renorm = 1;
   o.gemm_cfg = -1;
   o.product = QPR_PRODUCT_AUTO;
+  o.integrator = QPR_RK4;
+  o.step_tol = 1e-4;
+  o.dt_max = 0.0;
   return o;
 }
 
@@ -407,8 +520,12 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   if (!rho) return fail(QPR_E_ARG, "rho must not be NULL");
   if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive (got %g)", tol);
   if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
-  if ((st = check_dt(P, omega, dt)) != QPR_OK) return st;
   qpr_opts o = opts ? *opts : default_opts();
+  if (o.integrator == QPR_RKF45) {
+    if (!(dt > 0.0)) return fail(QPR_E_ARG, "dt must be positive (got %g)", dt);
+  } else if ((st = check_dt(P, omega, dt)) != QPR_OK) {
+    return st;
+  }
   if (o.chunk <= 0) o.chunk = 64;
   if (o.fold_every <= 0) o.fold_every = o.chunk;
   hipStream_t s = (hipStream_t)stream;
@@ -423,7 +540,31 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   double* out_r = w.yn_r;
   double* out_i = w.yn_i;
   double* out_p = w.p_n;
-  if (prec == QPR_FP64) {
+  if (o.integrator == QPR_RKF45) {
+    if (prec != QPR_FP64) return fail(QPR_E_ARG, "the RKF45 integrator runs in FP64 only");
+    if (!(o.step_tol > 0.0)) return fail(QPR_E_ARG, "step_tol must be positive");
+    double hmax = o.dt_max;
+    if (!(hmax > 0.0)) hmax = rkf_step_cap(omega, P->h_norm);
+    if (!(hmax > 0.0)) return fail(QPR_E_UNSTABLE, "no stable Fehlberg step at omega=%g", omega);
+    QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_RKF, s));
+    QPR_HIP(launch_state_rkf(w.st, std::min(dt, hmax), hmax, o.step_tol, s));
+    QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
+    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
+      for (int k = 0; k < o.chunk; ++k) {
+        hipError_t e = enqueue_rkf_attempt(P, w, pv, omega, o.gemm_cfg, o.product, q);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    if (st != QPR_OK) return st;
+    S.steps = fs.accepted;
+    S.rejected = fs.rejected;
+    S.rhs_evals = 6 * (fs.accepted + fs.rejected) + 1;
+    S.rhs_evals_fp64 = S.rhs_evals;
+    S.residual = std::sqrt(fs.resid2);
+    S.last_step = fs.h;
+  } else if (prec == QPR_FP64) {
     QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_PLAIN, s));
     QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
     auto chunk_fn = [&](hipStream_t q) -> hipError_t {
@@ -505,11 +646,21 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
     S.herm_err = hs.aux[1];
     S.min_diag = hs.aux[2];
   }
-  S.t = (double)S.steps * dt;
+  S.t = o.integrator == QPR_RKF45 ? fs.t : (double)S.steps * dt;
   S.status = result;
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = S;
   return result;
+}
+
+extern "C" qpr_status qpr_hub_counts(int32_t n, const double* p, double c, int32_t* counts,
+                                      qpr_stream_t stream) {
+  clear_error();
+  if (n < 1) return fail(QPR_E_ARG, "n must be >= 1");
+  if (!p || !counts) return fail(QPR_E_ARG, "p and counts must not be NULL");
+  if (!(c > 1.0)) return fail(QPR_E_ARG, "c must be > 1 (got %g)", c);
+  QPR_HIP(launch_hubs(n, p, c, counts, (hipStream_t)stream));
+  return QPR_OK;
 }
 
 extern "C" qpr_status qpr_rank(int32_t n, const double* p, int32_t* order, qpr_stream_t stream) {

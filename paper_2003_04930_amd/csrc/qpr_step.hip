@@ -51,17 +51,20 @@ __device__ __forceinline__ void split3(double v, uint16_t& s1, uint16_t& s2, uin
 }
 
 // Two-level reduction over the `nb` tiles of one system: every tile writes its
-// partial, takes a ticket, and the tile that takes the last ticket sums all
-// partials in index order (deterministic).
-__device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double* partials,
-                                               DevState* st, double* red, int* flag,
-                                               double& tot, int& bad, int tile, int nb) {
+// partials (sum, non-finite flag, max), takes a ticket, and the tile that
+// takes the last ticket combines all partials in index order (deterministic).
+__device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double my_max,
+                                               double* partials, DevState* st, double* red,
+                                               int* flag, double& tot, int& bad, double& mx,
+                                               int tile, int nb) {
   const int tid = threadIdx.x;
   double s = block_sum(my_sum, red, ETHREADS / 64);
+  double m = block_max(my_max, red, ETHREADS / 64);
   int b = __syncthreads_or(my_bad);
   if (tid == 0) {
-    partials[2 * tile] = s;
-    partials[2 * tile + 1] = (double)b;
+    partials[3 * tile] = s;
+    partials[3 * tile + 1] = (double)b;
+    partials[3 * tile + 2] = m;
     __threadfence();
     const unsigned int t = atomicAdd(&st->ticket, 1u);
     *flag = (t == (unsigned int)(nb - 1));
@@ -69,32 +72,53 @@ __device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double
   __syncthreads();
   tot = 0.0;
   bad = 0;
+  mx = 0.0;
   if (*flag) {
     __threadfence();
-    double acc = 0.0, bb = 0.0;
+    double acc = 0.0, bb = 0.0, mm = 0.0;
     for (int i = tid; i < nb; i += ETHREADS) {
-      acc += partials[2 * i];
-      bb = fmax(bb, partials[2 * i + 1]);
+      acc += partials[3 * i];
+      bb = fmax(bb, partials[3 * i + 1]);
+      mm = fmax(mm, partials[3 * i + 2]);
     }
     tot = block_sum(acc, red, ETHREADS / 64);
+    mx = block_max(mm, red, ETHREADS / 64);
     bad = __syncthreads_or(bb != 0.0);
   }
 }
 
+// Tile pairs of the upper triangle: k -> (I, J), I <= J, column by column.
+__device__ __forceinline__ void tri_decode(int k, int& I, int& J) {
+  int j = (int)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= k) ++j;
+  while (j * (j + 1) / 2 > k) --j;
+  J = j;
+  I = k - j * (j + 1) / 2;
+}
+__host__ __device__ constexpr int tri_tiles(int t) { return t * (t + 1) / 2; }
+
+// One tile pair {(I, J), (J, I)}, I <= J, of the right-hand side and its RK4
+// stage.  The state is Hermitian and L maps Hermitian to (bitwise) Hermitian,
+// so only (I, J) is evaluated: y_n, the accumulator and the anchor residual
+// are read there only (the accumulator is only ever stored there), while the
+// next stage state -- which the product reads in full -- is written to (I, J)
+// and, conjugated, to (J, I).
 template <int XS>
 __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs& a,
                                               DevState* __restrict__ st,
                                               double* __restrict__ partials, int tile,
                                               int ntiles) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
+  __shared__ double Or[TE][TE + 1], Oi[TE][TE + 1];
   __shared__ double gs[TE];
   __shared__ double red[ETHREADS / 64];
   __shared__ int flag;
   const int tid = threadIdx.x, tx = tid & (TE - 1), ty = tid / TE;
   const int n = pv.n, ld = pv.ld;
-  const int tiles = ld / TE;
-  const int I = tile % tiles, J = tile / tiles;
+  int I, J;
+  tri_decode(tile, I, J);
   const int a0 = I * TE, b0 = J * TE;
+  const bool diag = I == J;
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
 #pragma unroll
@@ -118,9 +142,22 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
     const double P = block_sum(sp, red, ETHREADS / 64);
     const double D = block_sum(sd, red, ETHREADS / 64);
-    if (tid < TE && a0 + tid < n) {
-      GainView gv{n, pv.teleport, pv.alpha, pv.inv_outdeg, pv.dangling, pv.in_ptr, pv.in_idx};
-      gs[tid] = gain_row(gv, a0 + tid, a.ps, P, D);
+    // one wave per row: the lanes stride the in-link list (hub rows have
+    // in-degrees of ~100), then a wave reduction
+    GainView gv{n, pv.teleport, pv.alpha, pv.inv_outdeg, pv.dangling, pv.in_ptr, pv.in_idx};
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int q = wave; q < TE; q += ETHREADS / 64) {
+      const int ar = a0 + q;
+      double sacc = 0.0;
+      if (ar < n) {
+        const int e1 = pv.in_ptr[ar + 1];
+        for (int e = pv.in_ptr[ar] + lane; e < e1; e += 64) {
+          const int j = pv.in_idx[e];
+          sacc += a.ps[j] * pv.inv_outdeg[j];
+        }
+      }
+      sacc = wave_sum_d(sacc);
+      if (lane == 0 && ar < n) gs[q] = gain_finish(gv, ar, a.ps, P, D, sacc);
     }
   }
   __syncthreads();
@@ -129,8 +166,10 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   const int b = b0 + tx;
   const bool bin = b < n;
   const double hb = bin ? pv.h[b] : 0.0, db = bin ? pv.d[b] : 0.0;
-  double ssum = 0.0;
+  double ssum = 0.0, emax = 0.0;
   int sbad = 0;
+  const int fstage = a.mode >= EPI_F1 ? a.mode - EPI_F1 + 1 : 0;  // Fehlberg stage 1..6
+  const double hstep = fstage ? st->h : 0.0;
 #pragma unroll
   for (int m = 0; m < TE / 8; ++m) {
     const int r = ty + 8 * m;
@@ -158,7 +197,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         kr += a.rar[o];
         ki += a.rai[o];
       }
-      ssum += kr * kr + ki * ki;
+      ssum += (diag ? 1.0 : 2.0) * (kr * kr + ki * ki);
       sbad |= !(isfinite(kr) && isfinite(ki));
     }
     double outr, outi;
@@ -180,10 +219,36 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         outr = a.ynr[o] + a.cdt * kr;
         outi = a.yni[o] + a.cdt * ki;
         break;
-      default:  // EPI_S4: y_{n+1} = y_n + dt/6 (acc + k4)
+      case EPI_S4:  // y_{n+1} = y_n + dt/6 (acc + k4)
         outr = a.ynr[o] + a.cdt * (a.accr[o] + kr);
         outi = a.yni[o] + a.cdt * (a.acci[o] + ki);
         break;
+      default: {  // Fehlberg stage fstage: K_s = k; next stage input, or at
+                  // stage 6 the fourth-order candidate and the error estimate
+        double sr = 0.0, si = 0.0, er = 0.0, ei = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+          if (j < fstage - 1) {
+            const double kjr = a.kr[j][o], kji = a.ki[j][o];
+            sr += a.cf[j] * kjr;
+            si += a.cf[j] * kji;
+            er += a.ce[j] * kjr;
+            ei += a.ce[j] * kji;
+          }
+        sr += a.cf[fstage - 1] * kr;
+        si += a.cf[fstage - 1] * ki;
+        er += a.ce[fstage - 1] * kr;
+        ei += a.ce[fstage - 1] * ki;
+        if (fstage < 6) {
+          a.kwr[o] = kr;
+          a.kwi[o] = ki;
+        } else if (inside) {
+          emax = fmax(emax, hstep * sqrt(er * er + ei * ei));
+        }
+        outr = a.ynr[o] + hstep * sr;
+        outi = a.yni[o] + hstep * si;
+        break;
+      }
     }
     if (!inside) {
       outr = 0.0;
@@ -191,6 +256,10 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
     a.outr[o] = outr;
     a.outi[o] = outi;
+    if (!diag) {
+      Or[r][tx] = outr;
+      Oi[r][tx] = outi;
+    }
     if (a.pout && inside && ar == b) a.pout[ar] = outr;
     if (a.lor) {
       a.lor[o] = (float)outr;
@@ -211,11 +280,62 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
   }
 
-  if (a.mode == EPI_S1 || a.mode == EPI_RHS) {
-    double tot;
+  if (!diag) {
+    // mirror tile (J, I) = conj of tile (I, J), written row-major through LDS
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < TE / 8; ++m) {
+      const int r = ty + 8 * m;
+      const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
+      const double outr = Or[tx][r], outi = -Oi[tx][r];
+      a.outr[o] = outr;
+      a.outi[o] = outi;
+      if (a.lor) {
+        a.lor[o] = (float)outr;
+        a.loi[o] = (float)outi;
+      }
+      if (a.slices) {
+        const size_t plane = (size_t)ld * ld;
+        uint16_t s1, s2, s3;
+        split3(outr, s1, s2, s3);
+        a.slices[o] = s1;
+        a.slices[plane + o] = s2;
+        a.slices[2 * plane + o] = s3;
+        split3(-outi, s1, s2, s3);
+        a.slices[3 * plane + o] = s1;
+        a.slices[4 * plane + o] = s2;
+        a.slices[5 * plane + o] = s3;
+      }
+    }
+  }
+
+  if (a.mode == EPI_S1 || a.mode == EPI_RHS || fstage == 1 || fstage == 6) {
+    double tot, mx;
     int bad;
-    last_block_sum(ssum, sbad, partials, st, red, &flag, tot, bad, tile, ntiles);
-    if (flag && tid == 0) {
+    last_block_sum(ssum, sbad, emax, partials, st, red, &flag, tot, bad, mx, tile, ntiles);
+    if (flag && tid == 0 && fstage == 6) {
+      // Fehlberg step control (Supplementary Note 2, Eq. (S13)): accept when
+      // |z - y| <= Tol h, next step h * (Tol h / (2 |z - y|))^(1/4), the factor
+      // clamped to [0.1, 4] and the step to h_max.
+      const double h = st->h, tolh = st->tol_step * h;
+      const int ok = !bad && mx <= tolh;
+      st->err = mx;
+      st->accept = ok;
+      if (ok) {
+        st->t += h;
+        st->accepted += 1;
+      } else {
+        st->rejected += 1;
+      }
+      if (bad) {
+        st->nonfinite = 1;
+        st->stop = 1;
+      }
+      double fac = mx > 0.0 ? pow(tolh / (2.0 * mx), 0.25) : 4.0;
+      fac = fmin(4.0, fmax(0.1, fac));
+      st->h = fmin(h * fac, st->h_max);
+      st->ticket = 0u;
+    } else if (flag && tid == 0) {
       st->resid2 = tot;
       st->rhs_evals += 1;
       if (bad) {
@@ -237,6 +357,16 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         // steps so the FP64 fold and judge run.
         if (tot < 0.81 * st->tol2 || st->step >= st->max_steps) st->hold = 1;
         else st->step += 1;
+      } else if (a.check == CHK_RKF) {
+        if (tot < st->tol2) {
+          st->converged = 1;
+          st->conv_step = st->accepted;
+          st->stop = 1;
+        } else if (st->step >= st->max_steps) {
+          st->stop = 1;
+        } else {
+          st->step += 1;  // attempts
+        }
       } else if (a.check == CHK_JUDGE) {
         st->judge2 = tot;
         st->folds += 1;
@@ -275,16 +405,15 @@ __global__ void __launch_bounds__(ETHREADS)
     const BatchEpi& e = args[item.x];
     DevState* st = e.st;
     if (st->stop || (e.a.gate && st->hold)) continue;
-    const int tiles = e.pv.ld / TE;
-    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y, tiles * tiles);
+    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y, tri_tiles(e.pv.ld / TE));
     __syncthreads();
   }
 }
 
 // Sparse commutator product X = H_off Y (FP64) through the CSR of H_off.
 // Workgroup (row a, 128-column chunk): thread t handles plane t / 128 and
-// column c0 + t % 128, summing the neighbour rows of a in CSR order with eight
-// independent loads in flight.  Rows a >= n are left untouched (the epilogue
+// column c0 + t % 128, summing the neighbour rows of a with sixteen
+// independent partial sums (fixed order, so the result is reproducible).  Rows a >= n are left untouched (the epilogue
 // never reads them).
 constexpr int SP_COLS = 128;
 __device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __restrict__ yr,
@@ -295,20 +424,23 @@ __device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __res
   const double* Y = t < SP_COLS ? yr : yi;
   const int ld = pv.ld;
   const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
+  // sixteen independent partial sums: sixteen loads in flight per thread
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
   int e = e0;
-  for (; e + 8 <= e1; e += 8) {
-    s0 += Y[(size_t)pv.h_idx[e + 0] * ld + c];
-    s1 += Y[(size_t)pv.h_idx[e + 1] * ld + c];
-    s2 += Y[(size_t)pv.h_idx[e + 2] * ld + c];
-    s3 += Y[(size_t)pv.h_idx[e + 3] * ld + c];
-    s4 += Y[(size_t)pv.h_idx[e + 4] * ld + c];
-    s5 += Y[(size_t)pv.h_idx[e + 5] * ld + c];
-    s6 += Y[(size_t)pv.h_idx[e + 6] * ld + c];
-    s7 += Y[(size_t)pv.h_idx[e + 7] * ld + c];
+  for (; e + 16 <= e1; e += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] += Y[(size_t)pv.h_idx[e + u] * ld + c];
   }
-  for (; e < e1; ++e) s0 += Y[(size_t)pv.h_idx[e] * ld + c];
-  const double v = (double)pv.hsign * (((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)));
+#pragma unroll
+  for (int u = 0; u < 15; ++u)
+    if (e + u < e1) acc[u] += Y[(size_t)pv.h_idx[e + u] * ld + c];
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+  const double v = (double)pv.hsign * acc[0];
   (t < SP_COLS ? xr : xi)[(size_t)a * ld + c] = v;
 }
 
@@ -403,6 +535,18 @@ __global__ void k_state_init(DevState* st, double tol, long long max_steps, int 
   st->judge2 = 0.0;
   st->folds = 0;
   for (int i = 0; i < 8; ++i) st->aux[i] = 0.0;
+}
+
+__global__ void k_state_rkf(DevState* st, double h0, double h_max, double tol_step) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->h = h0;
+  st->h_max = h_max;
+  st->tol_step = tol_step;
+  st->t = 0.0;
+  st->err = 0.0;
+  st->accepted = 0;
+  st->rejected = 0;
+  st->accept = 0;
 }
 
 // st->aux[0] = sum_a p_a (one workgroup, fixed order); skipped once stopped
@@ -504,6 +648,48 @@ __global__ void __launch_bounds__(256) k_rank(int n, const double* __restrict__ 
   if (i < n) order[cnt] = i;
 }
 
+// Hub classes of the results section: counts of p_i > c/N (main hubs) and
+// 1/N < p_i <= c/N (secondary hubs); one workgroup, out[0..1] (device ints).
+__global__ void __launch_bounds__(1024) k_hubs(int n, const double* __restrict__ p, double c,
+                                               int* __restrict__ out) {
+  __shared__ int red[2][1024];
+  const int t = threadIdx.x;
+  const double hi = c / (double)n, lo = 1.0 / (double)n;
+  int m = 0, s2 = 0;
+  for (int i = t; i < n; i += 1024) {
+    const double v = p[i];
+    m += v > hi;
+    s2 += (v > lo) && (v <= hi);
+  }
+  red[0][t] = m;
+  red[1][t] = s2;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) {
+      red[0][t] += red[0][t + off];
+      red[1][t] += red[1][t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+// Fehlberg: y <- candidate when the attempt was accepted (and not stopped)
+__global__ void k_rkf_commit(double* __restrict__ yr, double* __restrict__ yi,
+                             double* __restrict__ p, const double* __restrict__ cr,
+                             const double* __restrict__ ci, const double* __restrict__ pc, int n,
+                             int ld, const DevState* __restrict__ st) {
+  if (st->stop || !st->accept) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ld * ld) return;
+  yr[idx] = cr[idx];
+  yi[idx] = ci[idx];
+  if (idx < (size_t)n) p[idx] = pc[idx];
+}
+
 __global__ void k_axpy_planes(double* __restrict__ yr, double* __restrict__ yi,
                               const double* __restrict__ xr, const double* __restrict__ xi,
                               double alpha, int n, int ld, double* __restrict__ p,
@@ -556,9 +742,8 @@ ProbView view_of(const qpr_problem* P) {
 }
 
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s) {
-  const int tiles = pv.ld / TE;
-  const int grid = tiles * tiles;
-  if (grid * 2 > w.max_partials) return hipErrorInvalidValue;
+  const int grid = tri_tiles(pv.ld / TE);
+  if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
   if (a.xkind == XS_DENSE64)
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_DENSE32)
@@ -578,6 +763,8 @@ hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, d
 }
 
 int spmm_items_per_system(int n, int ld) { return n * ((ld + SP_COLS - 1) / SP_COLS); }
+
+int epilogue_items_per_system(int ld) { return tri_tiles(ld / TE); }
 
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
                              hipStream_t s) {
@@ -631,6 +818,11 @@ hipError_t launch_state_init(DevState* st, double tol, long long max_steps, int 
   return hipGetLastError();
 }
 
+hipError_t launch_state_rkf(DevState* st, double h0, double h_max, double tol_step, hipStream_t s) {
+  k_state_rkf<<<1, 64, 0, s>>>(st, h0, h_max, tol_step);
+  return hipGetLastError();
+}
+
 hipError_t launch_state_stats(const double* r, const double* i, const double* p, int n, int ld,
                               const Ws& w, hipStream_t s) {
   int grid = blocks_for((size_t)n * n, 256);
@@ -642,6 +834,18 @@ hipError_t launch_state_stats(const double* r, const double* i, const double* p,
 
 hipError_t launch_rank(int n, const double* p, int* order, hipStream_t s) {
   k_rank<<<blocks_for((size_t)n, 256), 256, 0, s>>>(n, p, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_rkf_commit(double* yr, double* yi, double* p, const double* cr,
+                             const double* ci, const double* pc, int n, int ld,
+                             const DevState* st, hipStream_t s) {
+  k_rkf_commit<<<blocks_for((size_t)ld * ld, 256), 256, 0, s>>>(yr, yi, p, cr, ci, pc, n, ld, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_hubs(int n, const double* p, double c, int* out, hipStream_t s) {
+  k_hubs<<<1, 1024, 0, s>>>(n, p, c, out);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ TELEPORT = {"paper_f": 0, "uniform": 1}
 HDIAG = {"zero": 0, "paper": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PRODUCT = {"auto": 0, "dense": 1, "sparse": 2}
+INTEGRATOR = {"rk4": 0, "rkf45": 1}
 
 # every symbol include/qpr.h declares
 EXPORTS = (
@@ -35,7 +36,7 @@ EXPORTS = (
     "qpr_time_kernels", "qpr_product_configs", "qpr_product_config_name",
     "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
     "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam", "qpr_autotune",
-    "qpr_load_tuning", "qpr_batch_workspace_bytes", "qpr_batch_solve",
+    "qpr_load_tuning", "qpr_batch_workspace_bytes", "qpr_batch_solve", "qpr_hub_counts",
 )
 
 
@@ -51,7 +52,8 @@ class qpr_problem(C.Structure):
         ("n", C.c_int32), ("ld", C.c_int32), ("n_edges_in", C.c_int64), ("nnz_a", C.c_int64),
         ("nnz_h", C.c_int64), ("n_self_loops", C.c_int32), ("n_dangling", C.c_int32),
         ("alpha", C.c_double), ("teleport", C.c_int32), ("hdiag", C.c_int32),
-        ("h_lo", C.c_double), ("h_hi", C.c_double), ("pagerank_iters", C.c_int32),
+        ("h_lo", C.c_double), ("h_hi", C.c_double), ("h_norm", C.c_double),
+        ("pagerank_iters", C.c_int32),
         ("reserved", C.c_int32),
         ("h_off", C.c_void_p), ("h_off_f32", C.c_void_p), ("h_off_bf16", C.c_void_p),
         ("h_diag", C.c_void_p), ("d", C.c_void_p), ("inv_outdeg", C.c_void_p),
@@ -69,6 +71,7 @@ class qpr_stats(C.Structure):
         ("folds", C.c_int64), ("t", C.c_double), ("residual", C.c_double),
         ("trace_err", C.c_double), ("herm_err", C.c_double), ("min_diag", C.c_double),
         ("seconds", C.c_double), ("converged", C.c_int32), ("status", C.c_int32),
+        ("rejected", C.c_int64), ("last_step", C.c_double),
     ]
 
     def as_dict(self):
@@ -85,7 +88,8 @@ class qpr_mpnn_batch(C.Structure):
 class qpr_opts(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("use_graph", C.c_int32), ("fold_every", C.c_int32),
                 ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("product", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("integrator", C.c_int32), ("reserved", C.c_int32), ("step_tol", C.c_double),
+                ("dt_max", C.c_double)]
 
 
 _lib = None
@@ -111,6 +115,7 @@ def lib():
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                    C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_rank": (i32, [i32, vp, vp, vp]),
+        "qpr_hub_counts": (i32, [i32, vp, dbl, vp, vp]),
         "qpr_time_kernels": (i32, [P, dbl, i32, i32, i32, vp, C.POINTER(C.c_double), vp, sz, vp]),
         "qpr_product_configs": (i32, [i32]),
         "qpr_autotune": (i32, [P, i32, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), vp,
@@ -275,9 +280,11 @@ def _planar_arg(rho, n):
 
 
 # --------------------------------------------------------------- entry points
-def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto"):
+def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto",
+              integrator="rk4", step_tol=1e-4, dt_max=0.0):
     return qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm),
-                    int(gemm_cfg), PRODUCT[product])
+                    int(gemm_cfg), PRODUCT[product], INTEGRATOR[integrator], 0,
+                    float(step_tol), float(dt_max))
 
 
 def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1):
@@ -316,7 +323,8 @@ class SolveResult:
 
 def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0=None,
                  want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1,
-                 allow_not_converged=False, product="auto"):
+                 allow_not_converged=False, product="auto", integrator="rk4", step_tol=1e-4,
+                 dt_max=0.0):
     torch = _torch()
     n = P.n
     if rho0 is None:
@@ -326,7 +334,8 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
         rho = _planar_arg(rho0, n).clone()
     rank = torch.empty(n, dtype=torch.int32, device="cuda") if want_rank else None
     st = qpr_stats()
-    op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product)
+    op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
+                   dt_max)
     ws = workspace(n, prec)
     status = lib().qpr_steady_state(C.byref(P.p), float(omega), float(dt), float(tol),
                                     int(max_steps), PREC[prec], _ptr(rho), _ptr(rank),
@@ -334,6 +343,16 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
                                     _stream())
     _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
     return SolveResult(rho, rank, st.as_dict(), status)
+
+
+def hub_counts(p, c=10.0):
+    """(main hubs, secondary hubs) of the populations p, counted on the GPU."""
+    torch = _torch()
+    p = p.to(torch.float64).contiguous()
+    out = torch.zeros(2, dtype=torch.int32, device=p.device)
+    _check(lib().qpr_hub_counts(int(p.numel()), _ptr(p), float(c), _ptr(out), _stream()))
+    a, b = out.cpu().tolist()
+    return int(a), int(b)
 
 
 def rank(p):

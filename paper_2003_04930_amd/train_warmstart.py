@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--load", default=None, help="skip training, evaluate these weights")
+    ap.add_argument("--data", default="batch", choices=["batch", "rkf45"],
+                    help="steady states for training: batched RK4 or single RKF45 solves")
     args = ap.parse_args()
     import torch
 
@@ -71,9 +73,15 @@ def main():
         targets = []
         step = 200
         for i in range(0, len(items), step):
-            res = Q.batch_solve(items[i:i + step], tol=1e-8, want_rank=False)
-            targets += [r[0].diagonal().to(torch.float32).clone() for r in res.rhos]
-            log(f"steady states {i + len(res.rhos)}/{len(items)} ({res.seconds:.1f} s)")
+            chunk = items[i:i + step]
+            t1 = time.perf_counter()
+            if args.data == "batch":
+                rhos = Q.batch_solve(chunk, tol=1e-8, want_rank=False).rhos
+            else:
+                rhos = [Q.steady_state(P, w, 0.01, 1e-8, 400000, want_rank=False,
+                                       integrator="rkf45").rho for P, w in chunk]
+            targets += [r[0].diagonal().to(torch.float32).clone() for r in rhos]
+            log(f"steady states {i + len(rhos)}/{len(items)} ({time.perf_counter() - t1:.1f} s)")
         t_data = time.perf_counter() - t0
         t1 = time.perf_counter()
         params, hist = W.train(items, targets, steps=args.steps, batch_graphs=args.batch_graphs,

@@ -182,6 +182,53 @@ def test_error_paths(Q):
     assert e.value.status == Q.QPR_E_ARG
 
 
+# ------------------------------------------------------ Fehlberg RKF45
+@pytest.mark.parametrize("product", ["dense", "sparse"])
+def test_rkf45_attempts_match_oracle(Q, product):
+    """The first attempts of the adaptive Fehlberg integration: same accepted
+    and rejected counts and the same state as the oracle's RKF45."""
+    g = GRAPHS["ba130"]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    omega, h0, tol_step, hmax = 0.7, 0.01, 1e-5, 0.25
+    f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
+    attempts = 25
+    y, t, acc, rej = O.rkf45_ref(np.eye(g.n) / g.n, f, h0, tol_step, tol_ss=1e-14,
+                                 max_steps=attempts, h_max=hmax, raise_on_limit=False)
+    out = Q.steady_state(P, omega, h0, 1e-14, attempts, integrator="rkf45", step_tol=tol_step,
+                         dt_max=hmax, product=product, allow_not_converged=True, chunk=7)
+    assert out.stats["steps"] == acc and out.stats["rejected"] == rej
+    assert abs(out.stats["t"] - t) < 1e-12
+    assert np.max(np.abs(Q.to_complex(out.rho) - y)) < 1e-12
+
+
+def test_rkf45_steady_state_matches_rk4_fixed_point(Q):
+    """RKF45 and RK4 share the fixed point L(rho) = 0; the adaptive run needs
+    far fewer steps."""
+    g = GRAPHS["ba300"]()
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    omega, tol = 0.5, 1e-10
+    rk4 = Q.steady_state(P, omega, 0.01, tol, 400000)
+    rkf = Q.steady_state(P, omega, 0.01, tol, 400000, integrator="rkf45", step_tol=1e-4)
+    a, b = Q.to_complex(rkf.rho), Q.to_complex(rk4.rho)
+    f = lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, omega)
+    assert np.sqrt(np.sum(np.abs(f(a)) ** 2)) < tol * (1 + 1e-6)
+    assert np.max(np.abs(a - b)) < 1e-9
+    assert rkf.stats["steps"] < rk4.stats["steps"] / 4
+    assert rkf.stats["herm_err"] == 0.0
+    assert list(rkf.rank.cpu().numpy()) == list(rk4.rank.cpu().numpy())
+
+
+def test_spectral_radius_estimate(Q):
+    for g in (GRAPHS["ba300"](), inputs.ba_digraph(922, 3, seed=0)):
+        for hdiag in ("zero", "paper"):
+            P = Q.Problem.from_graph(g, hdiag=hdiag)
+            R = oracle_problem(g, hdiag=hdiag)
+            rho = np.max(np.abs(np.linalg.eigvalsh(R.H)))
+            assert 0.97 * rho <= P.p.h_norm <= rho * (1 + 1e-9)
+
+
 # ---------------------------------------------------------------- ranking
 def test_rank_kernel_with_ties(Q):
     rng = np.random.default_rng(0)
@@ -189,6 +236,15 @@ def test_rank_kernel_with_ties(Q):
         p = rng.integers(0, max(2, n // 5), size=n).astype(np.float64) / 7.0  # many ties
         got = Q.rank(torch.from_numpy(p).cuda()).cpu().numpy()
         assert list(got) == list(O.rank_ref(p))
+
+
+def test_hub_counts_match_oracle(Q):
+    rng = np.random.default_rng(1)
+    for n in (10, 500, 3000):
+        p = rng.dirichlet(np.full(n, 0.3))
+        p[:3] = [10.0 / n, 1.0 / n, 10.0 / n + 1e-12]   # boundary values
+        got = Q.hub_counts(torch.from_numpy(p).cuda(), 10.0)
+        assert got == O.hub_classes_ref(p, 10.0)
 
 
 # --------------------------------------------------------- full-size cases
