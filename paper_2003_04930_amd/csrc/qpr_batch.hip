@@ -103,7 +103,7 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
     SysInfo si;
     si.n = ns[s];
     si.ld = pad_n(ns[s]);
-    si.ws_size = ws_bytes(ns[s], prec);
+    si.ws_size = ws_bytes(ns[s], prec, false);
     si.ws_off = take(si.ws_size);
     L.sys.push_back(si);
     const size_t tg = (size_t)(si.ld / gtile) * (si.ld / gtile);
@@ -209,7 +209,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   for (int k = 0; k < nsys; ++k) {
     const qpr_problem* P = probs[k];
     Ws& w = W[k];
-    if (!ws_carve(base + L.sys[k].ws_off, L.sys[k].ws_size, P->n, prec, &w))
+    if (!ws_carve(base + L.sys[k].ws_off, L.sys[k].ws_size, P->n, prec, &w, false))
       return fail(QPR_E_WORKSPACE, "system %d: workspace carve failed", k);
     w.st = states + k;
     const ProbView pv = view_of(P);

@@ -90,8 +90,9 @@ struct Ws {
   double* scal = nullptr;                    // small scratch (16 doubles)
 };
 
-size_t ws_bytes(int n, int prec);
-bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* out);
+// rkf: include the Fehlberg planes (single solves); the batched solve omits them
+size_t ws_bytes(int n, int prec, bool rkf = true);
+bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* out, bool rkf = true);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().

@@ -74,7 +74,10 @@ __device__ __forceinline__ void gemm_k4_tile(const T* __restrict__ H, const T* _
   constexpr int EV = M::EV;
   constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int AP = BM + EV, BP = BN + EV;
+  // rows padded by 16 elements: lane groups reading consecutive k-rows of a
+  // fragment land 32 banks apart (64-bank LDS), so a half-wave read is
+  // conflict-free for both FP64 and FP32
+  constexpr int AP = BM + 16, BP = BN + 16;
   constexpr int NA = BK * BM / EV / NT, NB = BK * BN / EV / NT;
   static_assert(NA * NT * EV == BK * BM && NB * NT * EV == BK * BN, "tile/thread mismatch");
   __shared__ T As[2][BK * AP];
@@ -336,6 +339,8 @@ const GemmCfg<F64Fn> kF64[] = {
     {32, 32, "f64_32x32_w16x16_k32", k_gemm_k4<double, 32, 32, 16, 16, 32>, 256},
     {64, 32, "f64_64x32_w32x16_k32", k_gemm_k4<double, 64, 32, 32, 16, 32>, 256},
     {32, 64, "f64_32x64_w16x32_k32", k_gemm_k4<double, 32, 64, 16, 32, 32>, 256},
+    {128, 128, "f64_128x128_w64x64_k16", k_gemm_k4<double, 128, 128, 64, 64>, 256},
+    {128, 64, "f64_128x64_w32x32_k16", k_gemm_k4<double, 128, 64, 32, 32>, 512},
 };
 const GemmCfg<F32Fn> kF32[] = {
     {64, 64, "f32_64x64_w32x32_k16", k_gemm_k4<float, 64, 64, 32, 32>, 256},

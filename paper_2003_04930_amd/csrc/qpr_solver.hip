@@ -59,7 +59,7 @@ struct WsLayout {
   int max_partials;
 };
 
-WsLayout ws_layout(int n, int prec) {
+WsLayout ws_layout(int n, int prec, bool rkf) {
   const size_t ld = (size_t)pad_n(n);
   const size_t pd = ld * ld * 8, pf = ld * ld * 4, ph = ld * ld * 2;
   WsLayout L{};
@@ -78,7 +78,7 @@ WsLayout ws_layout(int n, int prec) {
     if (prec == QPR_BF16X3) L.sl = take(6 * ph);
   }
   L.pv = take(4 * ld * 8);
-  if (prec == QPR_FP64) {  // Fehlberg: K_1..K_5, candidate state and its diagonal
+  if (prec == QPR_FP64 && rkf) {  // Fehlberg: K_1..K_5, candidate state and its diagonal
     L.kf = take(10 * pd);
     L.cand = take(2 * pd);
     L.pc = take(ld * 8);
@@ -93,10 +93,10 @@ WsLayout ws_layout(int n, int prec) {
 }
 }  // namespace
 
-size_t ws_bytes(int n, int prec) { return ws_layout(n, prec).total; }
+size_t ws_bytes(int n, int prec, bool rkf) { return ws_layout(n, prec, rkf).total; }
 
-bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w) {
-  const WsLayout L = ws_layout(n, prec);
+bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
+  const WsLayout L = ws_layout(n, prec, rkf);
   if (bytes < L.total) return false;
   char* b = (char*)base;
   const size_t ld = (size_t)pad_n(n);
@@ -132,7 +132,7 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w) {
   w->p_1 = pv + ld;
   w->p_2 = pv + 2 * ld;
   w->p_a = pv + 3 * ld;
-  if (prec == QPR_FP64) {
+  if (prec == QPR_FP64 && rkf) {
     double* kf = (double*)(b + L.kf);
     for (int j = 0; j < 5; ++j) {
       w->k_r[j] = kf + (2 * j) * pl;

@@ -170,32 +170,61 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   int sbad = 0;
   const int fstage = a.mode >= EPI_F1 ? a.mode - EPI_F1 + 1 : 0;  // Fehlberg stage 1..6
   const double hstep = fstage ? st->h : 0.0;
+  // All loads of this thread's four elements are issued before any store:
+  // outputs may alias inputs (y_n is updated in place at the last RK4 stage),
+  // so the compiler could not reorder them across the stores itself.
+  constexpr int EM = TE / 8;
+  const bool need_yn = a.mode != EPI_RHS;
+  const bool need_acc = a.mode == EPI_S2 || a.mode == EPI_S3 || a.mode == EPI_S4;
+  double xa[EM], xb[EM], yr_[EM], yi_[EM], nr_[EM], ni_[EM], cr_[EM], ci_[EM], rr_[EM], ri_[EM];
 #pragma unroll
-  for (int m = 0; m < TE / 8; ++m) {
+  for (int m = 0; m < EM; ++m) {
+    const int ar = a0 + ty + 8 * m;
+    const size_t o = (size_t)ar * ld + b;
+    xa[m] = xb[m] = yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
+    if (bin && ar < n) {
+      if (XS != XS_DENSE32) {
+        xa[m] = a.xr[o];
+        xb[m] = a.xi[o];
+      } else {
+        xa[m] = (double)a.xfr[o];
+        xb[m] = (double)a.xfi[o];
+      }
+      yr_[m] = a.ysr[o];
+      yi_[m] = a.ysi[o];
+      if (a.rar) {
+        rr_[m] = a.rar[o];
+        ri_[m] = a.rai[o];
+      }
+    }
+    if (need_yn) {
+      nr_[m] = a.ynr[o];
+      ni_[m] = a.yni[o];
+    }
+    if (need_acc) {
+      cr_[m] = a.accr[o];
+      ci_[m] = a.acci[o];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < EM; ++m) {
     const int r = ty + 8 * m;
     const int ar = a0 + r;
     const size_t o = (size_t)ar * ld + b;
     double kr = 0.0, ki = 0.0;
     const bool inside = bin && ar < n;
     if (inside) {
-      double A_ab, B_ab;
-      if (XS != XS_DENSE32) {
-        A_ab = a.xr[o];
-        B_ab = a.xi[o];
-      } else {
-        A_ab = (double)a.xfr[o];
-        B_ab = (double)a.xfi[o];
-      }
+      const double A_ab = xa[m], B_ab = xb[m];
       const double A_ba = Tr[tx][r], B_ba = Ti[tx][r];
-      const double R = a.ysr[o], Im = a.ysi[o];
+      const double R = yr_[m], Im = yi_[m];
       const double hab = pv.h[ar] - hb;
       const double dab = 0.5 * (pv.d[ar] + db);
       const double gd = (ar == b) ? gs[r] : 0.0;
       kr = cw * ((B_ab + B_ba) + hab * Im) + w * (gd - dab * R);
       ki = cw * ((A_ba - A_ab) - hab * R) - w * (dab * Im);
       if (a.rar) {
-        kr += a.rar[o];
-        ki += a.rai[o];
+        kr += rr_[m];
+        ki += ri_[m];
       }
       ssum += (diag ? 1.0 : 2.0) * (kr * kr + ki * ki);
       sbad |= !(isfinite(kr) && isfinite(ki));
@@ -209,19 +238,19 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
       case EPI_S1:
         a.accr[o] = kr;
         a.acci[o] = ki;
-        outr = a.ynr[o] + a.cdt * kr;
-        outi = a.yni[o] + a.cdt * ki;
+        outr = nr_[m] + a.cdt * kr;
+        outi = ni_[m] + a.cdt * ki;
         break;
       case EPI_S2:
       case EPI_S3:
-        a.accr[o] += 2.0 * kr;
-        a.acci[o] += 2.0 * ki;
-        outr = a.ynr[o] + a.cdt * kr;
-        outi = a.yni[o] + a.cdt * ki;
+        a.accr[o] = cr_[m] + 2.0 * kr;
+        a.acci[o] = ci_[m] + 2.0 * ki;
+        outr = nr_[m] + a.cdt * kr;
+        outi = ni_[m] + a.cdt * ki;
         break;
       case EPI_S4:  // y_{n+1} = y_n + dt/6 (acc + k4)
-        outr = a.ynr[o] + a.cdt * (a.accr[o] + kr);
-        outi = a.yni[o] + a.cdt * (a.acci[o] + ki);
+        outr = nr_[m] + a.cdt * (cr_[m] + kr);
+        outi = ni_[m] + a.cdt * (ci_[m] + ki);
         break;
       default: {  // Fehlberg stage fstage: K_s = k; next stage input, or at
                   // stage 6 the fourth-order candidate and the error estimate
@@ -245,8 +274,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         } else if (inside) {
           emax = fmax(emax, hstep * sqrt(er * er + ei * ei));
         }
-        outr = a.ynr[o] + hstep * sr;
-        outi = a.yni[o] + hstep * si;
+        outr = nr_[m] + hstep * sr;
+        outi = ni_[m] + hstep * si;
         break;
       }
     }
@@ -412,8 +441,9 @@ __global__ void __launch_bounds__(ETHREADS)
 
 // Sparse commutator product X = H_off Y (FP64) through the CSR of H_off.
 // Workgroup (row a, 128-column chunk): thread t handles plane t / 128 and
-// column c0 + t % 128, summing the neighbour rows of a with sixteen
-// independent partial sums (fixed order, so the result is reproducible).  Rows a >= n are left untouched (the epilogue
+// column c0 + t % 128, summing the neighbour rows of a with eight independent
+// partial sums (fixed order, so the result is reproducible).  Eight keeps the
+// kernel at 8 waves per SIMD; sixteen measured slower.  Rows a >= n are left untouched (the epilogue
 // never reads them).
 constexpr int SP_COLS = 128;
 __device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __restrict__ yr,
@@ -424,23 +454,20 @@ __device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __res
   const double* Y = t < SP_COLS ? yr : yi;
   const int ld = pv.ld;
   const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
-  // sixteen independent partial sums: sixteen loads in flight per thread
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
   int e = e0;
-  for (; e + 16 <= e1; e += 16) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] += Y[(size_t)pv.h_idx[e + u] * ld + c];
+  for (; e + 8 <= e1; e += 8) {
+    s0 += Y[(size_t)pv.h_idx[e + 0] * ld + c];
+    s1 += Y[(size_t)pv.h_idx[e + 1] * ld + c];
+    s2 += Y[(size_t)pv.h_idx[e + 2] * ld + c];
+    s3 += Y[(size_t)pv.h_idx[e + 3] * ld + c];
+    s4 += Y[(size_t)pv.h_idx[e + 4] * ld + c];
+    s5 += Y[(size_t)pv.h_idx[e + 5] * ld + c];
+    s6 += Y[(size_t)pv.h_idx[e + 6] * ld + c];
+    s7 += Y[(size_t)pv.h_idx[e + 7] * ld + c];
   }
-#pragma unroll
-  for (int u = 0; u < 15; ++u)
-    if (e + u < e1) acc[u] += Y[(size_t)pv.h_idx[e + u] * ld + c];
-#pragma unroll
-  for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-    for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
-  const double v = (double)pv.hsign * acc[0];
+  for (; e < e1; ++e) s0 += Y[(size_t)pv.h_idx[e] * ld + c];
+  const double v = (double)pv.hsign * (((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)));
   (t < SP_COLS ? xr : xi)[(size_t)a * ld + c] = v;
 }
 
