@@ -140,7 +140,9 @@ typedef struct {
   int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1]  */
   int32_t product;    /* qpr_product [QPR_PRODUCT_AUTO]                       */
   int32_t integrator; /* qpr_integrator [QPR_RK4]                             */
-  int32_t reserved;
+  int32_t sparse_variant; /* sparse product kernel variant + 1, 0 = default [0];
+                             variants as listed under qpr_time_kernels;
+                             single-system calls only                    */
   double step_tol;    /* RKF45: local error tolerance per unit step [1e-4]    */
   double dt_max;      /* RKF45: step cap; 0 = from the spectral radius of H [0] */
 } qpr_opts;
@@ -329,7 +331,13 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * then `reps` launches of the fused epilogue of an interior stage (reads
  * Y_s, y_n and the accumulator, writes the accumulator and Y_{s+1}, plus X
  * for the dense product).  cfg = -2 with QPR_FP64 times the sparse product
- * (CSR gathers of rho through the pattern of H_off) in place of the dense one.
+ * (CSR gathers of rho through the pattern of H_off) in place of the dense one;
+ * cfg = -3 - v times sparse-product variant v: 0 cm_w32_r1, 1 cm_w64_r1,
+ * 2 cm_w128_r1, 3 cm_w64_r2 (column-chunk major, XCD-aware: W columns of
+ * both planes per wave, R rows per wave), 4 row128 (one workgroup per row and
+ * 128-column chunk).  The default is row128 below N = 1536 and cm_w128_r1 above where
+ * the padded size is a multiple of 128.  All variants give bitwise the same
+ * product.
  *   rho     device, 2*n*n planar FP64 operand (unchanged)
  *   ms_out  HOST double[2]: mean milliseconds per product launch and per
  *           epilogue launch

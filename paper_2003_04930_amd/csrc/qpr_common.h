@@ -105,6 +105,7 @@ struct ProbView {
   const int *dangling, *in_ptr, *in_idx;
   int hsign;                 // value of every nonzero of H_off (+1 or -1)
   const int *h_ptr, *h_idx;  // CSR pattern of H_off
+  int spmm_variant;          // sparse-product variant, -1 = the default one
 };
 ProbView view_of(const qpr_problem* P);
 
@@ -195,8 +196,11 @@ hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,
                              const int* nitems, int grid, hipStream_t s);
 hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* items,
                                  const int* nitems, int grid, hipStream_t s);
+// variant: index into the sparse-product variants (-1 = pv.spmm_variant)
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
-                       double* xi, const DevState* st, int gate, hipStream_t s);
+                       double* xi, const DevState* st, int gate, hipStream_t s, int variant = -1);
+int spmm_num_variants();
+const char* spmm_variant_name(int v);
 int spmm_items_per_system(int n, int ld);
 int epilogue_items_per_system(int ld);
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,

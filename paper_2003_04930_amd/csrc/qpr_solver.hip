@@ -48,6 +48,15 @@ static bool use_sparse(const qpr_problem* P, int product, int xk) {
   return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
 }
 
+// The problem view with the sparse-product variant the options ask for.
+static qpr_status view_for(const qpr_problem* P, const qpr_opts& o, ProbView* pv) {
+  *pv = view_of(P);
+  if (o.sparse_variant < 0 || o.sparse_variant > spmm_num_variants())
+    return fail(QPR_E_ARG, "sparse_variant must be in [0, %d]", spmm_num_variants());
+  pv->spmm_variant = o.sparse_variant - 1;
+  return QPR_OK;
+}
+
 static int op_kind(int prec) {
   return prec == QPR_FP32 ? OP_F32 : prec == QPR_BF16X3 ? OP_BF16X3 : OP_F64;
 }
@@ -401,7 +410,8 @@ extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* 
   if (!rho || !out) return fail(QPR_E_ARG, "rho and out must not be NULL");
   if (rho == out) return fail(QPR_E_ARG, "rho and out must not alias");
   hipStream_t s = (hipStream_t)stream;
-  const ProbView pv = view_of(P);
+  ProbView pv;
+  if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
   QPR_HIP(launch_state_init(w.st, 0.0, 0, 0, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
   QPR_HIP(enqueue_rhs(P, w, pv, omega, w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, op_kind(prec), o.gemm_cfg,
@@ -423,7 +433,8 @@ extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt
   if (nsteps < 0) return fail(QPR_E_ARG, "nsteps must be >= 0");
   if ((st = check_dt(P, omega, dt)) != QPR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const ProbView pv = view_of(P);
+  ProbView pv;
+  if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
   const int xk = op_kind(prec);
   QPR_HIP(launch_state_init(w.st, 0.0, nsteps, 0, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
@@ -529,7 +540,8 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   if (o.chunk <= 0) o.chunk = 64;
   if (o.fold_every <= 0) o.fold_every = o.chunk;
   hipStream_t s = (hipStream_t)stream;
-  const ProbView pv = view_of(P);
+  ProbView pv;
+  if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
   const int n = P->n, ld = P->ld;
   qpr_stats S{};
   qpr_status result = QPR_OK;
@@ -707,7 +719,10 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   a.omega = omega;
   a.cdt = 0.005;
   a.mode = EPI_S2;  // an interior stage: reads Y_s, y_n, acc (+ X), writes acc and Y_{s+1}
-  const bool sparse = cfg == -2 && xk == OP_F64;  // -2: time the sparse fused stage instead
+  // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v
+  const bool sparse = cfg <= -2 && xk == OP_F64;
+  const int spv = cfg <= -3 ? -3 - cfg : -1;
+  if (sparse && spv >= spmm_num_variants()) return fail(QPR_E_ARG, "no such sparse-product variant");
   a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
   a.lor = xk == OP_F32 ? w.lo_r : nullptr;
   a.loi = xk == OP_F32 ? w.lo_i : nullptr;
@@ -716,7 +731,7 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   for (auto& e : ev) QPR_HIP(hipEventCreate(&e));
   auto product = [&]() {
-    return sparse ? launch_spmm(pv, w.y1_r, w.y1_i, w.x_r, w.x_i, w.st, 0, s)
+    return sparse ? launch_spmm(pv, w.y1_r, w.y1_i, w.x_r, w.x_i, w.st, 0, s, spv)
                   : launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s);
   };
   for (int r = 0; r < 3; ++r) QPR_HIP(product());

@@ -142,23 +142,36 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
     const double P = block_sum(sp, red, ETHREADS / 64);
     const double D = block_sum(sd, red, ETHREADS / 64);
-    // one wave per row: the lanes stride the in-link list (hub rows have
-    // in-degrees of ~100), then a wave reduction
+    // eight lanes per row, all 32 rows at once: lane k of a row takes in-links
+    // k, k + 8, ... (four in flight), then a reduction over the eight lanes in
+    // a fixed order.  The row sums are the critical path of a diagonal tile.
     GainView gv{n, pv.teleport, pv.alpha, pv.inv_outdeg, pv.dangling, pv.in_ptr, pv.in_idx};
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int q = wave; q < TE; q += ETHREADS / 64) {
-      const int ar = a0 + q;
-      double sacc = 0.0;
-      if (ar < n) {
-        const int e1 = pv.in_ptr[ar + 1];
-        for (int e = pv.in_ptr[ar] + lane; e < e1; e += 64) {
-          const int j = pv.in_idx[e];
-          sacc += a.ps[j] * pv.inv_outdeg[j];
-        }
+    static_assert(ETHREADS == 8 * TE, "eight lanes per row of the tile");
+    const int q = tid >> 3, k = tid & 7;
+    const int ar = a0 + q;
+    double sacc = 0.0;
+    if (ar < n) {
+      const int e1 = pv.in_ptr[ar + 1];
+      int e = pv.in_ptr[ar] + k;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      for (; e + 24 < e1; e += 32) {
+        const int j0 = pv.in_idx[e], j1 = pv.in_idx[e + 8], j2 = pv.in_idx[e + 16],
+                  j3 = pv.in_idx[e + 24];
+        t0 += a.ps[j0] * pv.inv_outdeg[j0];
+        t1 += a.ps[j1] * pv.inv_outdeg[j1];
+        t2 += a.ps[j2] * pv.inv_outdeg[j2];
+        t3 += a.ps[j3] * pv.inv_outdeg[j3];
       }
-      sacc = wave_sum_d(sacc);
-      if (lane == 0 && ar < n) gs[q] = gain_finish(gv, ar, a.ps, P, D, sacc);
+      for (; e < e1; e += 8) {
+        const int j = pv.in_idx[e];
+        t0 += a.ps[j] * pv.inv_outdeg[j];
+      }
+      sacc = (t0 + t1) + (t2 + t3);
     }
+    sacc += __shfl_xor(sacc, 1, 64);
+    sacc += __shfl_xor(sacc, 2, 64);
+    sacc += __shfl_xor(sacc, 4, 64);
+    if (k == 0 && ar < n) gs[q] = gain_finish(gv, ar, a.ps, P, D, sacc);
   }
   __syncthreads();
 
@@ -440,35 +453,161 @@ __global__ void __launch_bounds__(ETHREADS)
 }
 
 // Sparse commutator product X = H_off Y (FP64) through the CSR of H_off.
-// Workgroup (row a, 128-column chunk): thread t handles plane t / 128 and
-// column c0 + t % 128, summing the neighbour rows of a with eight independent
-// partial sums (fixed order, so the result is reproducible).  Eight keeps the
-// kernel at 8 waves per SIMD; sixteen measured slower.  Rows a >= n are left untouched (the epilogue
-// never reads them).
+// Row a of X is the sum of the rows j of Y with (H_off)_aj != 0 (all entries
+// are +-1), so the product is a gather: per output element, deg_H(a) loads.
+//
+// The neighbour list of a row is taken in groups of eight whose loads are all
+// issued before any is used (see gather_rows for the short last group).
+// Element e of the list goes to partial sum (e - e0) % 8 and the partials are
+// added as ((0+1)+(2+3))+((4+5)+(6+7)): every variant gives bitwise the same X.
+//
+// Variants (one wave per (row, W columns of both planes) unless noted):
+//  * column-chunk major (SpmmCM<W, RPW>): W = 32: lanes 0-31 take the real
+//    plane, 32-63 the imaginary one; W = 64: lane l column l of both planes;
+//    W = 128: lane l columns 2l, 2l+1 of both planes.  RPW rows per wave, four
+//    waves per workgroup.  Workgroups are numbered chunk-major and remapped so
+//    that each XCD (dispatch is round-robin over the 8 XCDs) owns a contiguous
+//    run of column chunks: the Y rows one XCD gathers at a time are a
+//    2 W x ld x 8-byte slice rather than the whole matrix.
+//  * row major: workgroup (row, 128-column chunk), 256 threads, thread t
+//    plane t / 128 and column t % 128; guarded (not predicated) short group.
+// Measured on BA graphs: the row-major kernel is fastest at N ~ 1000 (the
+// predicated loads cost more than the latency they hide there), 128-column
+// chunks at N >= 2048.
+// Rows a >= n are left untouched (the epilogue never reads them).
 constexpr int SP_COLS = 128;
-__device__ __forceinline__ void spmm_row(const ProbView& pv, const double* __restrict__ yr,
-                                         const double* __restrict__ yi, double* __restrict__ xr,
-                                         double* __restrict__ xi, int a, int chunk) {
-  const int t = threadIdx.x, c = chunk * SP_COLS + (t & (SP_COLS - 1));
-  if (c >= pv.ld) return;
-  const double* Y = t < SP_COLS ? yr : yi;
-  const int ld = pv.ld;
-  const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
+constexpr int SP_WAVES = 4;
+
+// Sum over the neighbour rows j of a of Y_s[j * ld] for S streams (pointers
+// already offset to the lane's column); the row range [e0, e1) is uniform.
+// Full groups of eight issue all their loads first.  The last, short group is
+// either predicated (PRED: eight loads, the missing ones repeating the last
+// neighbour and masked out) or taken one guarded load at a time (no extra
+// requests; better where the memory system rather than latency is the limit).
+template <int S, bool PRED>
+__device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e0, int e1, int ld,
+                                            const double* const (&base)[S], double (&out)[S]) {
+  double acc[8][S];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[k][q] = 0.0;
   int e = e0;
   for (; e + 8 <= e1; e += 8) {
-    s0 += Y[(size_t)pv.h_idx[e + 0] * ld + c];
-    s1 += Y[(size_t)pv.h_idx[e + 1] * ld + c];
-    s2 += Y[(size_t)pv.h_idx[e + 2] * ld + c];
-    s3 += Y[(size_t)pv.h_idx[e + 3] * ld + c];
-    s4 += Y[(size_t)pv.h_idx[e + 4] * ld + c];
-    s5 += Y[(size_t)pv.h_idx[e + 5] * ld + c];
-    s6 += Y[(size_t)pv.h_idx[e + 6] * ld + c];
-    s7 += Y[(size_t)pv.h_idx[e + 7] * ld + c];
+    size_t off[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) off[k] = (size_t)h_idx[e + k] * ld;
+    double v[8][S];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < S; ++q) v[k][q] = base[q][off[k]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc[k][q] += v[k][q];
   }
-  for (; e < e1; ++e) s0 += Y[(size_t)pv.h_idx[e] * ld + c];
-  const double v = (double)pv.hsign * (((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)));
-  (t < SP_COLS ? xr : xi)[(size_t)a * ld + c] = v;
+  if (e < e1) {
+    if (PRED) {
+      size_t off[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) off[k] = (size_t)h_idx[min(e + k, e1 - 1)] * ld;
+      double v[8][S];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < S; ++q) v[k][q] = base[q][off[k]];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < S; ++q) acc[k][q] += e + k < e1 ? v[k][q] : 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+        if (e + k < e1) {
+          const size_t o = (size_t)h_idx[e + k] * ld;
+#pragma unroll
+          for (int q = 0; q < S; ++q) acc[k][q] += base[q][o];
+        }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+    out[q] = ((acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q])) +
+             ((acc[4][q] + acc[5][q]) + (acc[6][q] + acc[7][q]));
+}
+
+template <int W>
+__device__ __forceinline__ void spmm_wave_row(const ProbView& pv, const double* __restrict__ yr,
+                                              const double* __restrict__ yi,
+                                              double* __restrict__ xr, double* __restrict__ xi,
+                                              int a, int chunk) {
+  const int l = threadIdx.x & 63;
+  const int ld = pv.ld;
+  const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
+  const double sg = (double)pv.hsign;
+  const size_t row = (size_t)a * ld;
+  if (W == 32) {
+    const int c = chunk * 32 + (l & 31);
+    const double* const b[1] = {(l < 32 ? yr : yi) + c};
+    double o[1];
+    gather_rows<1, true>(pv.h_idx, e0, e1, ld, b, o);
+    (l < 32 ? xr : xi)[row + c] = sg * o[0];
+  } else if (W == 64) {
+    const int c = chunk * 64 + l;
+    const double* const b[2] = {yr + c, yi + c};
+    double o[2];
+    gather_rows<2, true>(pv.h_idx, e0, e1, ld, b, o);
+    xr[row + c] = sg * o[0];
+    xi[row + c] = sg * o[1];
+  } else {
+    const int c = chunk * 128 + 2 * l;
+    const double* const b[4] = {yr + c, yr + c + 1, yi + c, yi + c + 1};
+    double o[4];
+    gather_rows<4, true>(pv.h_idx, e0, e1, ld, b, o);
+    *(double2*)(xr + row + c) = make_double2(sg * o[0], sg * o[1]);
+    *(double2*)(xi + row + c) = make_double2(sg * o[2], sg * o[3]);
+  }
+}
+
+// Workgroups per column chunk for the chunk-major variants.
+template <int RPW>
+__host__ __device__ __forceinline__ int spmm_cm_groups(int n) {
+  return (n + SP_WAVES * RPW - 1) / (SP_WAVES * RPW);
+}
+
+// One logical workgroup (chunk, row group) of a chunk-major variant.
+template <int W, int RPW>
+__device__ __forceinline__ void spmm_cm_group(const ProbView& pv, const double* __restrict__ yr,
+                                              const double* __restrict__ yi,
+                                              double* __restrict__ xr, double* __restrict__ xi,
+                                              int logical) {
+  const int groups = spmm_cm_groups<RPW>(pv.n);
+  const int chunk = logical / groups, g = logical - chunk * groups;
+  // the row index is uniform over the wave: keep it (and the CSR reads) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int a0 = (g * SP_WAVES + wave) * RPW;
+#pragma unroll 1
+  for (int r = 0; r < RPW; ++r) {
+    const int a = a0 + r;
+    if (a >= pv.n) return;
+    spmm_wave_row<W>(pv, yr, yi, xr, xi, a, chunk);
+  }
+}
+
+__device__ __forceinline__ int spmm_xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <int W, int RPW>
+__global__ void __launch_bounds__(64 * SP_WAVES)
+    k_spmm_cm(ProbView pv, const double* __restrict__ yr, const double* __restrict__ yi,
+              double* __restrict__ xr, double* __restrict__ xi, const DevState* __restrict__ st,
+              int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  spmm_cm_group<W, RPW>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x, gridDim.x));
 }
 
 __global__ void __launch_bounds__(2 * SP_COLS)
@@ -477,11 +616,18 @@ __global__ void __launch_bounds__(2 * SP_COLS)
            int gate) {
   if (st->stop || (gate && st->hold)) return;
   const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
-  spmm_row(pv, yr, yi, xr, xi, blockIdx.x / chunks, blockIdx.x % chunks);
+  const int a = __builtin_amdgcn_readfirstlane(blockIdx.x / chunks);
+  const int t = threadIdx.x, c = (blockIdx.x % chunks) * SP_COLS + (t & (SP_COLS - 1));
+  if (c >= pv.ld) return;
+  const double* const b[1] = {(t < SP_COLS ? yr : yi) + c};
+  double o[1];
+  gather_rows<1, false>(pv.h_idx, pv.h_ptr[a], pv.h_ptr[a + 1], pv.ld, b, o);
+  (t < SP_COLS ? xr : xi)[(size_t)a * pv.ld + c] = (double)pv.hsign * o[0];
 }
 
-// Persistent form over (system, row * chunks + chunk) items.
-__global__ void __launch_bounds__(2 * SP_COLS)
+// Persistent form over (system, chunk * groups + group) items of the W = 32,
+// RPW = 1 chunk-major variant (batched systems are small: no XCD remap).
+__global__ void __launch_bounds__(64 * SP_WAVES)
     k_spmm_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
                  const int* __restrict__ nitems) {
   const int ni = *nitems;
@@ -489,9 +635,7 @@ __global__ void __launch_bounds__(2 * SP_COLS)
     const int2 item = items[it];
     const BatchEpi& e = args[item.x];
     if (e.st->stop || (e.a.gate && e.st->hold)) continue;
-    const int chunks = (e.pv.ld + SP_COLS - 1) / SP_COLS;
-    spmm_row(e.pv, e.a.ysr, e.a.ysi, (double*)e.a.xr, (double*)e.a.xi, item.y / chunks,
-             item.y % chunks);
+    spmm_cm_group<32, 1>(e.pv, e.a.ysr, e.a.ysi, (double*)e.a.xr, (double*)e.a.xi, item.y);
   }
 }
 
@@ -765,7 +909,7 @@ ProbView view_of(const qpr_problem* P) {
   return ProbView{P->n,        P->ld,       P->teleport, P->alpha,
                   P->h_diag,   P->d,        P->inv_outdeg, P->dangling,
                   P->in_ptr,   P->in_idx,   P->hdiag == QPR_HDIAG_PAPER ? -1 : 1,
-                  P->h_ptr,    P->h_idx};
+                  P->h_ptr,    P->h_idx,    -1};
 }
 
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s) {
@@ -782,20 +926,60 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
   return hipGetLastError();
 }
 
+namespace {
+typedef void (*SpmmFn)(ProbView, const double*, const double*, double*, double*, const DevState*,
+                       int);
+struct SpmmVariant {
+  const char* name;
+  SpmmFn fn;
+  int cols, rpw;  // cols = 0: the legacy row-major kernel
+};
+const SpmmVariant kSpmm[] = {
+    {"cm_w32_r1", k_spmm_cm<32, 1>, 32, 1},
+    {"cm_w64_r1", k_spmm_cm<64, 1>, 64, 1},
+    {"cm_w128_r1", k_spmm_cm<128, 1>, 128, 1},
+    {"cm_w64_r2", k_spmm_cm<64, 2>, 64, 2},
+    {"row128", k_spmm, 0, 0},
+};
+constexpr int kNumSpmm = (int)(sizeof(kSpmm) / sizeof(kSpmm[0]));
+}  // namespace
+
+int spmm_num_variants() { return kNumSpmm; }
+const char* spmm_variant_name(int v) { return v >= 0 && v < kNumSpmm ? kSpmm[v].name : nullptr; }
+
+// Default by size (measured, BA graphs): the row-major kernel up to N ~ 1000,
+// 128-column chunks where ld is a multiple of 128 and the matrix is large.
+int spmm_default_variant(const ProbView& pv) {
+  return pv.ld % 128 == 0 && pv.n >= 1536 ? 2 : 4;
+}
+
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
-                       double* xi, const DevState* st, int gate, hipStream_t s) {
-  const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
-  k_spmm<<<pv.n * chunks, 2 * SP_COLS, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+                       double* xi, const DevState* st, int gate, hipStream_t s, int variant) {
+  if (variant < 0) variant = pv.spmm_variant >= 0 ? pv.spmm_variant : spmm_default_variant(pv);
+  if (variant >= kNumSpmm) return hipErrorInvalidValue;
+  // ld is a multiple of 64 only: a 128-column chunk size that does not divide
+  // it falls back to 64 columns (same sums, same bits)
+  if (kSpmm[variant].cols == 128 && pv.ld % 128 != 0) variant = 1;  // cm_w64_r1
+  const SpmmVariant& v = kSpmm[variant];
+  int grid;
+  if (v.cols == 0) {
+    grid = pv.n * ((pv.ld + SP_COLS - 1) / SP_COLS);
+    v.fn<<<grid, 2 * SP_COLS, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+  } else {
+    const int groups = (pv.n + SP_WAVES * v.rpw - 1) / (SP_WAVES * v.rpw);
+    grid = (pv.ld / v.cols) * groups;
+    v.fn<<<grid, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+  }
   return hipGetLastError();
 }
 
-int spmm_items_per_system(int n, int ld) { return n * ((ld + SP_COLS - 1) / SP_COLS); }
+int spmm_items_per_system(int n, int ld) { return (ld / 32) * spmm_cm_groups<1>(n); }
 
 int epilogue_items_per_system(int ld) { return tri_tiles(ld / TE); }
 
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
                              hipStream_t s) {
-  k_spmm_batch<<<grid, 2 * SP_COLS, 0, s>>>(args, items, nitems);
+  k_spmm_batch<<<grid, 64 * SP_WAVES, 0, s>>>(args, items, nitems);
   return hipGetLastError();
 }
 

@@ -10,8 +10,10 @@ device-to-device copy of --copy-mb MiB so the counters can be calibrated
 against a kernel whose traffic is known (copy reads and writes exactly that
 many bytes).
 
-Kernels: sparse (fused sparse RK4 stage), dense (FP64 MFMA product plus the
-dense epilogue), bf16x3 / fp32 (low-precision products plus epilogue).
+Kernels: sparse (sparse product plus the epilogue of an interior RK4 stage;
+--variant picks the sparse-product kernel variant, default the library's),
+dense (FP64 MFMA product plus the epilogue), bf16x3 / fp32 (low-precision
+products plus the epilogue).
 """
 from __future__ import annotations
 
@@ -29,6 +31,8 @@ def main():
     ap.add_argument("--kernel", default="sparse", choices=["sparse", "dense", "fp32", "bf16x3"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=256)
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="sparse-product variant index (-1 = default)")
     args = ap.parse_args()
     import torch
     from paper_2003_04930_amd import inputs, qpr as Q
@@ -37,7 +41,7 @@ def main():
     P = Q.Problem.from_graph(g)
     rho = Q.planar(inputs.random_density(args.n, seed=1))
     prec = {"sparse": "fp64", "dense": "fp64"}.get(args.kernel, args.kernel)
-    cfg = -2 if args.kernel == "sparse" else -1
+    cfg = (-2 if args.variant < 0 else -3 - args.variant) if args.kernel == "sparse" else -1
     prod_ms, epi_ms = Q.time_kernels(P, 0.8, rho, prec=prec, cfg=cfg, reps=args.reps)
     nbytes = args.copy_mb << 20
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -45,7 +49,7 @@ def main():
     torch.cuda.synchronize()
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"[profile] n={args.n} kernel={args.kernel} reps={args.reps} "
+    print(f"[profile] n={args.n} kernel={args.kernel} variant={args.variant} reps={args.reps} "
           f"product_us={prod_ms * 1e3:.2f} epilogue_us={epi_ms * 1e3:.2f} "
           f"copy_bytes={nbytes}", flush=True)
 

@@ -88,7 +88,7 @@ class qpr_mpnn_batch(C.Structure):
 class qpr_opts(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("use_graph", C.c_int32), ("fold_every", C.c_int32),
                 ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("product", C.c_int32),
-                ("integrator", C.c_int32), ("reserved", C.c_int32), ("step_tol", C.c_double),
+                ("integrator", C.c_int32), ("sparse_variant", C.c_int32), ("step_tol", C.c_double),
                 ("dt_max", C.c_double)]
 
 
@@ -280,20 +280,25 @@ def _planar_arg(rho, n):
 
 
 # --------------------------------------------------------------- entry points
+# sparse-product kernel variants (index v = option value v + 1; -1 = default)
+SPARSE_VARIANTS = ("cm_w32_r1", "cm_w64_r1", "cm_w128_r1", "cm_w64_r2", "row128")
+
+
 def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto",
-              integrator="rk4", step_tol=1e-4, dt_max=0.0):
+              integrator="rk4", step_tol=1e-4, dt_max=0.0, sparse_variant=-1):
     return qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm),
-                    int(gemm_cfg), PRODUCT[product], INTEGRATOR[integrator], 0,
-                    float(step_tol), float(dt_max))
+                    int(gemm_cfg), PRODUCT[product], INTEGRATOR[integrator],
+                    int(sparse_variant) + 1, float(step_tol), float(dt_max))
 
 
-def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1):
+def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1,
+        sparse_variant=-1):
     torch = _torch()
     rho = _planar_arg(rho, P.n)
     if out is None:
         out = torch.empty_like(rho)
     ws = workspace(P.n, prec)
-    op = make_opts(gemm_cfg=gemm_cfg, product=product)
+    op = make_opts(gemm_cfg=gemm_cfg, product=product, sparse_variant=sparse_variant)
     _check(lib().qpr_rhs(C.byref(P.p), float(omega), _ptr(rho), _ptr(out), PREC[prec],
                          C.byref(op), C.c_void_p(ws.ptr), ws.nbytes, _stream()))
     return out

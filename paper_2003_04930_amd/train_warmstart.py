@@ -9,9 +9,10 @@
 2. Training: Adam on the mean per-graph KL divergence, all on the GPU through
    the library's forward/backward/Adam kernels.
 3. Gain: on unseen graphs (seeds 20000.., N log-uniform in [50, n_max]) the
-   FP64 steady-state solve runs from rho0 = I/N, from diag(PageRank) and from
-   diag(p_hat); the steps to the tolerance are compared (the solve always
-   finishes and judges in FP64, so every start reaches the same state).
+   FP64 steady-state solve runs from rho0 = I/N, from diag(PageRank), from
+   diag(p_hat) and from the omega-blended start (warmstart.blend_weight); the
+   steps to the tolerance are compared (the solve always finishes and judges
+   in FP64, so every start reaches the same state; rankings are compared).
 
 Prints one JSON line with the summary.
 """
@@ -102,31 +103,48 @@ def main():
         g = test_graph(k, args.n_max_test)
         P = Q.Problem.from_graph(g)
         w = inputs.BATCH_OMEGAS[k % len(inputs.BATCH_OMEGAS)]
-        cold = Q.steady_state(P, w, 0.01, 1e-8, 400000, want_rank=False)
+        cold = Q.steady_state(P, w, 0.01, 1e-8, 400000)
         pr = Q.steady_state(P, w, 0.01, 1e-8, 400000, rho0=W.pagerank_rho0(P), want_rank=False)
+        raw = Q.steady_state(P, w, 0.01, 1e-8, 400000, rho0=W.warm_rho0(P, w, params, blend=False),
+                             want_rank=False)
         t0 = time.perf_counter()
         rho0 = W.warm_rho0(P, w, params)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
-        warm = Q.steady_state(P, w, 0.01, 1e-8, 400000, rho0=rho0, want_rank=False)
+        warm = Q.steady_state(P, w, 0.01, 1e-8, 400000, rho0=rho0)
         err = float((warm.rho - cold.rho).abs().max())
         rows.append({"n": g.n, "omega": w, "cold": cold.stats["steps"], "pagerank": pr.stats["steps"],
-                     "warm": warm.stats["steps"], "cold_s": cold.stats["seconds"],
-                     "warm_s": warm.stats["seconds"] + t_inf, "max_drho": err})
-        log(f"test {k}: n={g.n} w={w} steps cold/pr/warm {rows[-1]['cold']}/"
-            f"{rows[-1]['pagerank']}/{rows[-1]['warm']}")
-    cold = np.array([r["cold"] for r in rows], float)
-    prs = np.array([r["pagerank"] for r in rows], float)
-    warm = np.array([r["warm"] for r in rows], float)
-    summary.update({
-        "test_systems": len(rows),
-        "mean_steps": {"identity": cold.mean(), "pagerank": prs.mean(), "mpnn": warm.mean()},
-        "mean_step_ratio_mpnn_vs_identity": float(np.mean(warm / cold)),
-        "mean_step_ratio_mpnn_vs_pagerank": float(np.mean(warm / prs)),
-        "fraction_improved_vs_identity": float(np.mean(warm < cold)),
-        "max_drho_warm_vs_cold": max(r["max_drho"] for r in rows),
-        "rows": rows,
-    })
+                     "raw": raw.stats["steps"], "warm": warm.stats["steps"],
+                     "cold_s": cold.stats["seconds"], "warm_s": warm.stats["seconds"] + t_inf,
+                     "max_drho": err, "rank_equal": bool(torch.equal(warm.rank, cold.rank))})
+        log(f"test {k}: n={g.n} w={w} steps cold/pr/raw/warm {rows[-1]['cold']}/"
+            f"{rows[-1]['pagerank']}/{rows[-1]['raw']}/{rows[-1]['warm']}")
+    if rows:
+        cold = np.array([r["cold"] for r in rows], float)
+        prs = np.array([r["pagerank"] for r in rows], float)
+        raw = np.array([r["raw"] for r in rows], float)
+        warm = np.array([r["warm"] for r in rows], float)
+        om = np.array([r["omega"] for r in rows], float)
+        by_omega = {}
+        for w in sorted(set(om.tolist())):
+            m = om == w
+            by_omega[str(w)] = {"systems": int(m.sum()),
+                                "ratio_warm_vs_identity": float(np.mean(warm[m] / cold[m])),
+                                "ratio_raw_vs_identity": float(np.mean(raw[m] / cold[m])),
+                                "ratio_pagerank_vs_identity": float(np.mean(prs[m] / cold[m]))}
+        summary.update({
+            "test_systems": len(rows),
+            "mean_steps": {"identity": cold.mean(), "pagerank": prs.mean(), "mpnn_raw": raw.mean(),
+                           "mpnn_blended": warm.mean()},
+            "mean_step_ratio_mpnn_vs_identity": float(np.mean(warm / cold)),
+            "mean_step_ratio_raw_vs_identity": float(np.mean(raw / cold)),
+            "mean_step_ratio_mpnn_vs_pagerank": float(np.mean(warm / prs)),
+            "fraction_improved_vs_identity": float(np.mean(warm < cold)),
+            "by_omega": by_omega,
+            "max_drho_warm_vs_cold": max(r["max_drho"] for r in rows),
+            "all_ranks_equal": all(r["rank_equal"] for r in rows),
+            "rows": rows,
+        })
     print(json.dumps(summary), flush=True)
 
 

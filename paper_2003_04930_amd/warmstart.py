@@ -12,6 +12,8 @@ module only orchestrates (batching, the step loop, saving weights).
 """
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 
 from . import qpr as Q
@@ -85,7 +87,7 @@ def train(items, targets, steps=2000, batch_graphs=32, lr=1e-3, seed=0, params=N
         Q.mpnn_adam(params, grads, m, v, step, lr=lr * decay ** (step - 1))
         losses.append(loss)
         if log and step % log == 0:
-            print(f"[warmstart] step {step} loss {loss.item():.4e}", flush=True)
+            print(f"[warmstart] step {step} loss {loss.item():.4e}", file=sys.stderr, flush=True)
     return params, [float(x) for x in torch.cat(losses).cpu()]
 
 
@@ -109,12 +111,32 @@ def predict(P, omega, params):
     return p / p.sum()
 
 
-def warm_rho0(P, omega, params):
-    """rho0 = diag(p_hat) as a planar (2, n, n) FP64 tensor."""
+def blend_weight(omega):
+    """Weight lambda(omega) of the predicted populations in the start state.
+
+    A start state diag(p) has no coherences, and [H, diag(p)] != 0 drives
+    coherent modes that the dissipator (strength omega) damps slowly, whereas
+    I/N commutes with H.  Integrating from rho0 = (1 - l) I/N + l diag(p_ss),
+    with the exact steady-state populations p_ss, takes monotonically more RK4
+    steps as l grows for omega <= 0.5 and fewer for omega >= 0.65 (BA and ER
+    graphs, N = 40-60): below the crossover no population guess, however good,
+    beats I/N.  So the prediction is used in full above omega = 0.65, not at
+    all below 0.45, and blended linearly in between.
+    """
+    return float(min(1.0, max(0.0, (omega - 0.45) / 0.2)))
+
+
+def warm_rho0(P, omega, params, blend=True):
+    """rho0 = (1 - l) I/N + l diag(p_hat) as a planar (2, n, n) FP64 tensor,
+    l = blend_weight(omega) (l = 1 if blend is False)."""
     torch = _torch()
-    p = predict(P, omega, params)
+    lam = blend_weight(omega) if blend else 1.0
     rho = torch.zeros((2, P.n, P.n), dtype=torch.float64, device="cuda")
-    rho[0].diagonal().copy_(p)
+    if lam > 0.0:
+        p = predict(P, omega, params)
+        rho[0].diagonal().copy_(lam * p + (1.0 - lam) / P.n)
+    else:
+        rho[0].diagonal().fill_(1.0 / P.n)
     return rho
 
 

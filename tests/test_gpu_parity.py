@@ -275,6 +275,40 @@ def test_rhs_full_size(Q, n, m):
         assert list(hi[hp[a]:hp[a + 1]]) == list(np.nonzero(R.H[a] - np.diag(np.diag(R.H))[a])[0])
 
 
+def _hub_and_isolated(n=200):
+    """Node 0 linked to nodes 1..n-11 (a 189-neighbour row: many full groups of
+    eight plus a ragged one), a chain 1 -> 2 -> ... -> n-11 and ten isolated
+    nodes (empty rows)."""
+    src = [0] * (n - 11) + list(range(1, n - 11))
+    dst = list(range(1, n - 10)) + list(range(2, n - 10))
+    return inputs.Graph(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
+
+
+@pytest.mark.parametrize("name", ["er70", "ba130", "hub_isolated", "ba922"])
+def test_sparse_variants_bitwise_equal(Q, name):
+    """Every sparse-product kernel variant sums each row in the same order, so
+    the right-hand side is bitwise the same; it matches the oracle."""
+    g = (_hub_and_isolated() if name == "hub_isolated" else
+         inputs.ba_digraph(922, 3, seed=0) if name == "ba922" else GRAPHS[name]())
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    rho = inputs.random_density(g.n, seed=11)
+    outs = [Q.to_complex(Q.rhs(P, 0.5, Q.planar(rho), product="sparse", sparse_variant=v))
+            for v in range(len(Q.SPARSE_VARIANTS))]
+    for v in range(1, len(outs)):
+        assert np.array_equal(outs[0], outs[v]), Q.SPARSE_VARIANTS[v]
+    want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.5)
+    assert np.max(np.abs(outs[0] - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_sparse_variant_out_of_range(Q):
+    g = GRAPHS["er16"]()
+    P = Q.Problem.from_graph(g)
+    rho = Q.planar(inputs.random_density(g.n, seed=1))
+    with pytest.raises(Q.QprError):
+        Q.rhs(P, 0.5, rho, product="sparse", sparse_variant=len(Q.SPARSE_VARIANTS))
+
+
 def test_steady_state_n922_properties(Q):
     """Config-2 graph at omega = 0.8 to 1e-8: residual re-measured by the
     oracle, trace, Hermiticity, positivity, and a step-locked prefix."""
