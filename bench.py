@@ -8,12 +8,17 @@ omega = 0.2, 0.5, 0.8, and ranked.  `value` is the mean time-to-steady-state
 per solve in seconds (inputs resident in HBM; host readback of the device
 flag once per chunk is part of it).
 
-Also reported (same graph, same omegas): the dense FP64 MFMA solve, the
-mixed-precision solves (BF16x3 and FP32 MFMA products with FP64 judge), the
+Also reported (same graph, same omegas): the paper's adaptive RKF45
+integrator, the accelerated solver (RKF45 from the learned, omega-blended
+warm start) with its ranking checked against the plain solve, the dense FP64
+MFMA solve, the mixed-precision solves (BF16x3 and FP32 MFMA products with
+FP64 judge), the same comparison at N = 4096 (BA m=4, omega = 0.8), the
 roofline of the dominant kernel of the timed path (timed with HIP events on
-the solve's stream), and the CPU oracle on a bounded sample of the workload.
+the stream the kernels run on), and the CPU oracle on a bounded sample of the
+workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mixed]
+                    [--no-dense] [--no-rkf45] [--no-4096] [--warm PATH|none]
 """
 from __future__ import annotations
 
@@ -29,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-steady-state N=922/4096: FP64 plain vs mixed+warm-start; solves/s"
 OMEGAS = (0.2, 0.5, 0.8)
 N, M_BA, DT, TOL = 922, 3, 0.01, 1e-8
+WEIGHTS = os.path.join(ROOT, "paper_2003_04930_amd", "weights", "mpnn_warmstart.npy")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
@@ -74,6 +80,87 @@ def cpu_baseline(g, gpu_steps):
     }
 
 
+def tie_aware_rank_check(p_ref, rank, tau, np):
+    """Adjacent pairs of the reference order whose gap exceeds tau but whose
+    order the tested ranking swaps (0 = the rankings agree up to ties)."""
+    n = len(p_ref)
+    pos = np.empty(n, dtype=np.int64)
+    pos[rank] = np.arange(n)
+    order = np.argsort(-p_ref, kind="stable")
+    bad = 0
+    for i in range(n - 1):
+        a, b = order[i], order[i + 1]
+        if p_ref[a] - p_ref[b] > tau and pos[a] > pos[b]:
+            bad += 1
+    return bad
+
+
+def accelerated(Q, W, P, params, plain, plain_value, torch, np):
+    """RKF45 from the omega-blended learned warm start (inference included)."""
+    t0 = time.perf_counter()
+    out = []
+    for w in OMEGAS:
+        rho0 = W.warm_rho0(P, w, params)
+        out.append(Q.steady_state(P, w, DT, TOL, 400000, rho0=rho0, integrator="rkf45"))
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / len(OMEGAS)
+    err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(out, plain))
+    exact = all(bool(torch.equal(a.rank, b.rank)) for a, b in zip(out, plain))
+    viol = 0
+    for a, b in zip(out, plain):
+        p_ref = b.rho[0].diagonal().cpu().numpy()
+        viol += tie_aware_rank_check(p_ref, a.rank.cpu().numpy(), 2 * err, np)
+    row = {"seconds_per_solve": t, "speedup_vs_plain_fp64": plain_value / t,
+           "accepted_steps": [r.stats["steps"] for r in out],
+           "blend_weights": [W.blend_weight(w) for w in OMEGAS],
+           "max_abs_drho_vs_plain": err, "ranking_identical": exact,
+           "order_violations_beyond_2maxdrho": viol,
+           "residuals": [r.stats["residual"] for r in out]}
+    log(f"accelerated (RKF45 + warm start): {t:.3f} s/solve ({plain_value / t:.1f}x), "
+        f"max|drho| {err:.1e}, ranking identical {exact}")
+    return row
+
+
+def n4096_rows(Q, inputs, params, torch, np, args):
+    """Config-3 graph N = 4096 at omega = 0.8: plain FP64 RK4 against RKF45,
+    the accelerated solve and (unless --no-mixed) the FP32 mixed solve."""
+    n, w = 4096, 0.8
+    Pn = Q.Problem.from_graph(inputs.ba_digraph(n, 4, seed=0))
+    torch.cuda.synchronize()
+    plain = Q.steady_state(Pn, w, DT, TOL, 400000)
+    torch.cuda.synchronize()
+    row = {"omega": w, "plain_fp64": {"seconds": plain.stats["seconds"],
+                                      "rk4_steps": plain.stats["steps"]}}
+    log(f"n=4096 plain fp64: {plain.stats['seconds']:.2f} s, {plain.stats['steps']} steps")
+    sp_ms, epi_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64", cfg=-2, reps=20)
+    row["stage_us"] = {"spmm": sp_ms * 1e3, "epilogue": epi_ms * 1e3,
+                       "spmm_GBs": 32.0 * n * n / (sp_ms * 1e-3) / 1e9,
+                       "epilogue_GBs": 58.0 * n * n / (epi_ms * 1e-3) / 1e9}
+    runs = {}
+    if not args.no_rkf45:
+        runs["fp64_rkf45"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, integrator="rkf45")
+        if params is not None:
+            from paper_2003_04930_amd import warmstart as W
+            runs["accelerated"] = lambda: Q.steady_state(
+                Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), integrator="rkf45")
+    if not args.no_mixed:
+        runs["mixed_fp32"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, prec="fp32")
+    for name, fn in runs.items():
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        err = float((r.rho - plain.rho).abs().max())
+        p_ref = plain.rho[0].diagonal().cpu().numpy()
+        row[name] = {"seconds": t, "steps": r.stats["steps"], "speedup_vs_plain": plain.stats["seconds"] / t,
+                     "max_abs_drho_vs_plain": err,
+                     "ranking_identical": bool(torch.equal(r.rank, plain.rank)),
+                     "order_violations_beyond_2maxdrho":
+                         tie_aware_rank_check(p_ref, r.rank.cpu().numpy(), 2 * err, np)}
+        log(f"n=4096 {name}: {t:.2f} s ({plain.stats['seconds'] / t:.1f}x), max|drho| {err:.1e}")
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,11 +169,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-rkf45", action="store_true",
+                    help="skip the adaptive-integrator and accelerated rows")
+    ap.add_argument("--no-4096", action="store_true", help="skip the N = 4096 rows")
     ap.add_argument("--batch-graphs", type=int, default=0,
                     help="also time qpr_batch_solve on this many family graphs x 5 omegas")
     ap.add_argument("--precision-n", type=int, default=0,
                     help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
-    ap.add_argument("--warm", default=None, help="warm-start weights (.npy) to time as well")
+    ap.add_argument("--warm", default=WEIGHTS,
+                    help="warm-start weights (.npy) for the accelerated rows, or 'none'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -133,10 +224,11 @@ def main():
     sp_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", cfg=-2, reps=200)
     gemm_ms, _ = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
     ld = P.ld
-    # algorithmic bytes per launch (interior stage):
-    #   epilogue: X read once (16 B/elem), Y_s, y_n, acc read on the upper
-    #   triangle (3 x 8 B/elem), acc written there (8), Y_s+1 written in full (16)
-    epi_bytes = 64.0 * N * N
+    # algorithmic bytes per epilogue launch, unique data per element, the
+    # mean over the four RK4 stages (X 16 B read in full; Y_s, y_n, acc on the
+    # upper triangle 8 B each; acc written there 8 B; Y_s+1 written in full
+    # 16 B): stage 1 48, stages 2-3 64, stage 4 56 -> 58 B per element
+    epi_bytes = 58.0 * N * N
     #   sparse product: each gathered row of Y read once from HBM (16 B/elem),
     #   X written (16 B/elem); the nnz_H-fold re-reads hit the caches
     sp_bytes = 32.0 * N * N
@@ -169,19 +261,30 @@ def main():
                       "frac": sp_gbs / HBM_PEAK_GBS, "bytes_per_launch": sp_bytes},
              "nnz_h": int(P.p.nnz_h), "ld": ld}
 
-    # the paper's own integrator: adaptive Fehlberg 4(5), FP64, same tolerance
-    t0f = time.perf_counter()
-    rf = [Q.steady_state(P, w, DT, TOL, 400000, integrator="rkf45") for w in OMEGAS]
-    torch.cuda.synchronize()
-    tf = (time.perf_counter() - t0f) / len(OMEGAS)
-    errf = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rf, results))
-    extra["fp64_rkf45"] = {"seconds_per_solve": tf,
-                           "accepted_steps": [r.stats["steps"] for r in rf],
-                           "rejected_steps": [r.stats["rejected"] for r in rf],
-                           "last_step": [r.stats["last_step"] for r in rf],
-                           "max_abs_drho_vs_rk4": errf, "speedup_vs_rk4": value / tf}
-    log(f"fp64 rkf45: {tf:.3f} s/solve, accepted {[r.stats['steps'] for r in rf]}, "
-        f"rejected {[r.stats['rejected'] for r in rf]}, max|drho| vs RK4 {errf:.1e}")
+    params = None
+    if args.warm and args.warm != "none" and not args.no_rkf45:
+        from paper_2003_04930_amd import warmstart as W
+        params = W.load(args.warm)
+
+    if not args.no_rkf45:
+        # the paper's own integrator: adaptive Fehlberg 4(5), FP64, same tolerance
+        t0f = time.perf_counter()
+        rf = [Q.steady_state(P, w, DT, TOL, 400000, integrator="rkf45") for w in OMEGAS]
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t0f) / len(OMEGAS)
+        errf = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rf, results))
+        extra["fp64_rkf45"] = {"seconds_per_solve": tf,
+                               "accepted_steps": [r.stats["steps"] for r in rf],
+                               "rejected_steps": [r.stats["rejected"] for r in rf],
+                               "last_step": [r.stats["last_step"] for r in rf],
+                               "max_abs_drho_vs_rk4": errf, "speedup_vs_rk4": value / tf}
+        log(f"fp64 rkf45: {tf:.3f} s/solve, accepted {[r.stats['steps'] for r in rf]}, "
+            f"rejected {[r.stats['rejected'] for r in rf]}, max|drho| vs RK4 {errf:.1e}")
+        if params is not None:
+            extra["accelerated"] = accelerated(Q, W, P, params, results, value, torch, np)
+
+    if not args.no_4096:
+        extra["n4096"] = n4096_rows(Q, inputs, params, torch, np, args)
 
     if not args.no_dense:
         t0d = time.perf_counter()
@@ -212,36 +315,35 @@ def main():
                 "speedup_vs_fp64": value / tm}
             log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
 
-    if args.warm:
-        from paper_2003_04930_amd import warmstart as W
-        params = W.load(args.warm)
-        for prec in ("fp64", "fp32"):
-            t0w = time.perf_counter()
-            rw = solve_all(Q, P, prec, rho0_fn=lambda w: W.warm_rho0(P, w, params))
-            torch.cuda.synchronize()
-            tw = (time.perf_counter() - t0w) / len(OMEGAS)
-            err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rw, results))
-            extra[f"warm_{prec}"] = {"seconds_per_solve": tw,
-                                     "rk4_steps": [r.stats["steps"] for r in rw],
-                                     "max_abs_drho_vs_cold_fp64": err,
-                                     "speedup_vs_cold_fp64": value / tw}
-            log(f"warm start {prec}: {tw:.3f} s/solve, steps {[r.stats['steps'] for r in rw]}")
-
     if args.batch_graphs:
         items = []
         for k in range(args.batch_graphs):
             Pk = Q.Problem.from_graph(inputs.batch_graph(k))
             items += [(Pk, w) for w in inputs.BATCH_OMEGAS]
-        for prec in ("fp64", "fp32"):
-            rb = Q.batch_solve(items, prec=prec, tol=TOL, want_rank=True)
+        runs = [("fp64", dict(prec="fp64")), ("fp64_rkf45", dict(prec="fp64", integrator="rkf45"))]
+        if params is not None:
+            runs.append(("fp64_rkf45_warm", dict(prec="fp64", integrator="rkf45", warm=True)))
+        if not args.no_mixed:
+            runs.append(("fp32", dict(prec="fp32")))
+        for name, kw in runs:
+            rho0s = None
+            t_inf = 0.0
+            if kw.pop("warm", False):
+                from paper_2003_04930_amd import warmstart as W
+                t0i = time.perf_counter()
+                rho0s = W.warm_rho0_batch(items, params)
+                torch.cuda.synchronize()
+                t_inf = time.perf_counter() - t0i
+            rb = Q.batch_solve(items, tol=TOL, want_rank=True, rho0s=rho0s, **kw)
             st = [x["steps"] for x in rb.stats]
-            extra[f"batch_{prec}"] = {
-                "systems": len(items), "seconds": rb.seconds,
-                "solves_per_s": len(items) / rb.seconds, "tuned_cfg": rb.tuned_cfg,
+            secs = rb.seconds + t_inf
+            extra[f"batch_{name}"] = {
+                "systems": len(items), "seconds": secs, "inference_seconds": t_inf,
+                "solves_per_s": len(items) / secs, "tuned_cfg": rb.tuned_cfg,
                 "steps_min_mean_max": [min(st), float(np.mean(st)), max(st)],
                 "sum_n2": int(sum(Pk.n ** 2 for Pk, _ in items))}
-            log(f"batch {prec}: {len(items)} systems in {rb.seconds:.2f} s "
-                f"({len(items) / rb.seconds:.2f} solves/s)")
+            log(f"batch {name}: {len(items)} systems in {secs:.2f} s "
+                f"({len(items) / secs:.2f} solves/s)")
 
     if args.precision_n:
         nP = args.precision_n
@@ -254,15 +356,8 @@ def main():
             err = float((r.rho - ref.rho).abs().max())
             # ranking agreement on pairs whose gap exceeds 2 max|drho| (tie classes below)
             p = p_ref.cpu().numpy()
-            pos = np.empty(nP, dtype=np.int64)
-            pos[r.rank.cpu().numpy()] = np.arange(nP)
             tau = 2 * err
-            order = np.argsort(-p, kind="stable")
-            bad = 0
-            for i in range(nP - 1):
-                a_, b_ = order[i], order[i + 1]
-                if p[a_] - p[b_] > tau and pos[a_] > pos[b_]:
-                    bad += 1
+            bad = tie_aware_rank_check(p, r.rank.cpu().numpy(), tau, np)
             ties = int(np.sum(np.diff(np.sort(p)) <= tau))
             row[prec] = {"seconds": r.stats["seconds"], "rk4_steps": r.stats["steps"],
                          "folds": r.stats["folds"], "max_abs_drho_vs_fp64": err,

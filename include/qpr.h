@@ -237,12 +237,19 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
                             const qpr_opts* opts, void* ws, size_t ws_bytes,
                             qpr_stream_t stream);
 
-/* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys). */
-size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec);
+/* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys)
+ * with these options (NULL = defaults; opts->integrator = QPR_RKF45 adds each
+ * system's Fehlberg stage planes).  0 for an invalid request. */
+size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
+                                 const qpr_opts* opts);
 
 /*
  * Solve nsys independent systems (problem probs[k] at omega omegas[k]) to the
- * steady state of Eq. (1) with RK4 (Supplementary Note 2) in shared launches:
+ * steady state of Eq. (1) with RK4 (Supplementary Note 2) or, with
+ * opts->integrator = QPR_RKF45 (FP64 only), the adaptive Fehlberg 4(5) of
+ * qpr_steady_state with a step size and step control per system (dt = first
+ * step, cap from the system's spectral bound unless opts->dt_max > 0; each
+ * replayed chunk holds opts->chunk attempts) in shared launches:
  * every stage kernel covers all running systems through a device-side
  * (system, tile) work list; chunks of `opts->chunk` steps are replayed as one
  * captured HIP graph, and between replays the lists are shrunk to the systems
@@ -324,12 +331,13 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
 /* ---------------------------------------------------------- measurement */
 
 /*
- * Time the two kernels of one right-hand-side stage on `stream` with HIP
- * events: `reps` back-to-back launches of the commutator product
- * X = H_off [Re rho | Im rho] (the real products of the coherent term of
- * Eq. (1)) at precision `prec` with tile configuration `cfg` (-1 = default),
- * then `reps` launches of the fused epilogue of an interior stage (reads
- * Y_s, y_n and the accumulator, writes the accumulator and Y_{s+1}, plus X
+ * Time the two kernels of the RK4 stages on `stream` with HIP events: `reps`
+ * back-to-back launches of the commutator product X = H_off [Re rho | Im rho]
+ * (the real products of the coherent term of Eq. (1)) at precision `prec`
+ * with tile configuration `cfg` (-1 = default), then the fused epilogues of
+ * `reps` classical RK4 steps (stages 1-4 in turn, stage 1 with its residual,
+ * trace and finiteness reductions; X held fixed; each reads Y_s, y_n and the
+ * accumulator, writes the accumulator and Y_{s+1}, plus X
  * for the dense product).  cfg = -2 with QPR_FP64 times the sparse product
  * (CSR gathers of rho through the pattern of H_off) in place of the dense one;
  * cfg = -3 - v times sparse-product variant v: 0 cm_w32_r1, 1 cm_w64_r1,
@@ -340,7 +348,7 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * product.
  *   rho     device, 2*n*n planar FP64 operand (unchanged)
  *   ms_out  HOST double[2]: mean milliseconds per product launch and per
- *           epilogue launch
+ *           epilogue launch (the mean over the four stages)
  * Errors: QPR_E_ARG, QPR_E_WORKSPACE, QPR_E_HIP.  Synchronises.
  */
 qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32_t prec,

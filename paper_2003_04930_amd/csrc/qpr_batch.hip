@@ -11,6 +11,9 @@
 //
 // Precision: FP64 (sparse or dense product, as for one system) or FP32
 // products with FP64 judging (the defect correction of the single solve).
+// Integrator: classical RK4 with the fixed step dt, or (FP64) the adaptive
+// Fehlberg 4(5) of the single solve, each system with its own step size and
+// step control in its control block.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -82,6 +85,33 @@ __global__ void __launch_bounds__(256) k_fold_batch(const BatchFold* __restrict_
   }
 }
 
+struct BatchCommit {    // one system's Fehlberg commit: y <- candidate when accepted
+  double *yr, *yi, *p;
+  const double *cr, *ci, *pc;
+  int n, ld;
+  const DevState* st;
+};
+
+// commit per (system, row block of 32 rows); skipped unless the attempt was
+// accepted (and the system still runs)
+__global__ void __launch_bounds__(256) k_commit_batch(const BatchCommit* __restrict__ c,
+                                                      const int2* __restrict__ items,
+                                                      const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchCommit& C = c[item.x];
+    if (C.st->stop || !C.st->accept) continue;
+    const size_t o0 = (size_t)item.y * TE * C.ld;
+    for (int e = threadIdx.x; e < TE * C.ld; e += 256) {
+      C.yr[o0 + e] = C.cr[o0 + e];
+      C.yi[o0 + e] = C.ci[o0 + e];
+    }
+    for (int a = item.y * TE + threadIdx.x; a < item.y * TE + TE && a < C.n; a += 256)
+      C.p[a] = C.pc[a];
+  }
+}
+
 struct SysInfo {
   int n, ld;
   size_t ws_off, ws_size;
@@ -89,12 +119,16 @@ struct SysInfo {
 
 struct BatchLayout {
   std::vector<SysInfo> sys;
-  size_t states, gemm_args, epi_args, fold_args, items_g, items_e, items_f, items_s, sys_list,
-      counts, total;
+  size_t states, gemm_args, epi_args, fold_args, commit_args, items_g, items_e, items_f, items_s,
+      sys_list, counts, total;
   size_t max_g, max_e, max_f, max_s;
 };
 
-BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
+// Stage argument slots per system: RK4 stages 0-3 and the judge (4), or the
+// six Fehlberg stages.
+constexpr int kSlots = 6;
+
+BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile, bool rkf) {
   BatchLayout L;
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
@@ -103,7 +137,7 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
     SysInfo si;
     si.n = ns[s];
     si.ld = pad_n(ns[s]);
-    si.ws_size = ws_bytes(ns[s], prec, false);
+    si.ws_size = ws_bytes(ns[s], prec, rkf);
     si.ws_off = take(si.ws_size);
     L.sys.push_back(si);
     const size_t tg = (size_t)(si.ld / gtile) * (si.ld / gtile);
@@ -113,9 +147,10 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
     L.max_s += (size_t)spmm_items_per_system(si.n, si.ld);
   }
   L.states = take((size_t)nsys * sizeof(DevState));
-  L.gemm_args = take((size_t)nsys * 5 * sizeof(BatchGemm));
-  L.epi_args = take((size_t)nsys * 5 * sizeof(BatchEpi));
+  L.gemm_args = take((size_t)nsys * kSlots * sizeof(BatchGemm));
+  L.epi_args = take((size_t)nsys * kSlots * sizeof(BatchEpi));
   L.fold_args = take((size_t)nsys * sizeof(BatchFold));
+  L.commit_args = take((size_t)nsys * sizeof(BatchCommit));
   L.items_g = take(L.max_g * sizeof(int2));
   L.items_e = take(L.max_e * sizeof(int2));
   L.items_f = take(L.max_f * sizeof(int2));
@@ -131,11 +166,14 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile) {
 
 using namespace qpr;
 
-extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec) {
+extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
+                                            const qpr_opts* opts) {
   if (nsys < 1 || !n || (prec != QPR_FP64 && prec != QPR_FP32)) return 0;
   for (int s = 0; s < nsys; ++s)
     if (n[s] < 2) return 0;
-  return batch_layout(nsys, n, prec, 32).total;
+  const bool rkf = opts && opts->integrator == QPR_RKF45;
+  if (rkf && prec != QPR_FP64) return 0;
+  return batch_layout(nsys, n, prec, 32, rkf).total;
 }
 
 extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* probs,
@@ -161,6 +199,10 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   o.product = QPR_PRODUCT_AUTO;
   if (opts) o = *opts;
   if (o.chunk <= 0) o.chunk = 32;
+  const bool rkf = o.integrator == QPR_RKF45;
+  if (rkf && prec != QPR_FP64) return fail(QPR_E_ARG, "the RKF45 integrator runs in FP64 only");
+  if (rkf && !(o.step_tol > 0.0)) return fail(QPR_E_ARG, "step_tol must be positive");
+  if (o.integrator != QPR_RK4 && !rkf) return fail(QPR_E_ARG, "unknown integrator %d", o.integrator);
   std::vector<int> ns(nsys);
   for (int s = 0; s < nsys; ++s) {
     const qpr_problem* P = probs[s];
@@ -170,11 +212,12 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       return fail(QPR_E_ARG, "system %d: omega must be in [0,1]", s);
     if (!rhos[s]) return fail(QPR_E_ARG, "system %d: rho must not be NULL", s);
     const double reach = dt * ((1.0 - omegas[s]) * (P->h_hi - P->h_lo) + 2.0 * omegas[s]);
-    if (!(dt > 0.0) || reach >= 2.8)
+    if (!(dt > 0.0)) return fail(QPR_E_ARG, "dt must be positive (got %g)", dt);
+    if (!rkf && reach >= 2.8)
       return fail(QPR_E_UNSTABLE, "system %d: dt=%g outside the RK4 stability bound", s, dt);
     ns[s] = P->n;
   }
-  const BatchLayout L = batch_layout(nsys, ns.data(), prec, 32);
+  const BatchLayout L = batch_layout(nsys, ns.data(), prec, 32, rkf);
   if (ws_bytes_ < L.total)
     return fail(QPR_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", ws_bytes_, L.total);
   hipStream_t s = (hipStream_t)stream;
@@ -183,6 +226,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   BatchGemm* d_gemm = (BatchGemm*)(base + L.gemm_args);
   BatchEpi* d_epi = (BatchEpi*)(base + L.epi_args);
   BatchFold* d_fold = (BatchFold*)(base + L.fold_args);
+  BatchCommit* d_commit = (BatchCommit*)(base + L.commit_args);
   int2* d_items_g = (int2*)(base + L.items_g);
   int2* d_items_e = (int2*)(base + L.items_e);
   int2* d_items_f = (int2*)(base + L.items_f);
@@ -201,18 +245,46 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   const bool step_sparse = !mixed && sparse_for(probs[0]);
   const bool judge_sparse = sparse_for(probs[0]);
 
-  // host argument tables: stage kinds 0..3 = RK4 stages, 4 = judge / RHS
+  // host argument tables: slots 0..3 = RK4 stages, 4 = judge / RHS; or the six
+  // Fehlberg stages
   std::vector<Ws> W(nsys);
-  std::vector<BatchGemm> hg((size_t)nsys * 5);
-  std::vector<BatchEpi> he((size_t)nsys * 5);
+  std::vector<BatchGemm> hg((size_t)nsys * kSlots);
+  std::vector<BatchEpi> he((size_t)nsys * kSlots);
   std::vector<BatchFold> hf(nsys);
+  std::vector<BatchCommit> hc(nsys);
+  std::vector<double> hmax(nsys, 0.0);
   for (int k = 0; k < nsys; ++k) {
     const qpr_problem* P = probs[k];
     Ws& w = W[k];
-    if (!ws_carve(base + L.sys[k].ws_off, L.sys[k].ws_size, P->n, prec, &w, false))
+    if (!ws_carve(base + L.sys[k].ws_off, L.sys[k].ws_size, P->n, prec, &w, rkf))
       return fail(QPR_E_WORKSPACE, "system %d: workspace carve failed", k);
     w.st = states + k;
     const ProbView pv = view_of(P);
+    if (rkf) {
+      hmax[k] = o.dt_max > 0.0 ? o.dt_max : rkf_step_cap(omegas[k], P->h_norm);
+      if (!(hmax[k] > 0.0))
+        return fail(QPR_E_UNSTABLE, "system %d: no stable Fehlberg step at omega=%g", k, omegas[k]);
+      for (int q = 0; q < 6; ++q) {
+        BatchGemm& g = hg[(size_t)q * nsys + k];
+        BatchEpi& e = he[(size_t)q * nsys + k];
+        e = BatchEpi{};
+        e.pv = pv;
+        e.st = w.st;
+        e.partials = w.partials;
+        e.a = rkf_stage_args(w, q, omegas[k], step_sparse);
+        g = BatchGemm{};
+        g.H = P->h_off;
+        g.yr = e.a.ysr;
+        g.yi = e.a.ysi;
+        g.xr = w.x_r;
+        g.xi = w.x_i;
+        g.ld = P->ld;
+        g.gate = 0;
+        g.st = w.st;
+      }
+      hc[k] = BatchCommit{w.yn_r, w.yn_i, w.p_n, w.cand_r, w.cand_i, w.p_c, P->n, P->ld, w.st};
+      continue;
+    }
     struct St {
       double *inr, *ini, *pin, *outr, *outi, *pout, cdt;
     };
@@ -289,12 +361,14 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   QPR_HIP(hipMemcpyAsync(d_gemm, hg.data(), hg.size() * sizeof(BatchGemm), hipMemcpyHostToDevice, s));
   QPR_HIP(hipMemcpyAsync(d_epi, he.data(), he.size() * sizeof(BatchEpi), hipMemcpyHostToDevice, s));
   QPR_HIP(hipMemcpyAsync(d_fold, hf.data(), hf.size() * sizeof(BatchFold), hipMemcpyHostToDevice, s));
+  QPR_HIP(hipMemcpyAsync(d_commit, hc.data(), hc.size() * sizeof(BatchCommit), hipMemcpyHostToDevice, s));
 
   // initial state of every system
   for (int k = 0; k < nsys; ++k) {
     const qpr_problem* P = probs[k];
     Ws& w = W[k];
-    QPR_HIP(launch_state_init(w.st, tol, max_steps, mixed ? CHK_DELTA : CHK_PLAIN, s));
+    QPR_HIP(launch_state_init(w.st, tol, max_steps, rkf ? CHK_RKF : mixed ? CHK_DELTA : CHK_PLAIN, s));
+    if (rkf) QPR_HIP(launch_state_rkf(w.st, std::min(dt, hmax[k]), hmax[k], o.step_tol, s));
     if (mixed) {
       const size_t plane = (size_t)P->ld * P->ld;
       QPR_HIP(launch_pad_in(rhos[k], P->n, P->ld, w.an_r, w.an_i, w.p_a, s));
@@ -394,7 +468,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
 
   auto enqueue_stage = [&](int q, hipStream_t qs) -> hipError_t {
     hipError_t e = hipSuccess;
-    const bool judge = q == 4;
+    const bool judge = !rkf && q == 4;
     const bool gemm = judge ? !judge_sparse : use_gemm;
     const bool spmm = judge ? judge_sparse : step_sparse;
     if (spmm) {
@@ -409,7 +483,9 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     }
     const int xs = judge ? (judge_sparse ? XS_SPARSE64 : XS_DENSE64)
                          : mixed ? XS_DENSE32 : step_sparse ? XS_SPARSE64 : XS_DENSE64;
-    return launch_epilogue_batch(xs, d_epi + (size_t)q * nsys, d_items_e, d_counts + 1, grid_e, qs);
+    const bool finish = rkf ? (q == 0 || q == 5) : (q == 0 || q == 4);
+    return launch_epilogue_batch(xs, d_epi + (size_t)q * nsys, d_items_e, d_counts + 1, grid_e,
+                                 d_sys_list, d_counts + 3, finish, qs);
   };
   auto enqueue_fold_judge = [&](hipStream_t qs) -> hipError_t {
     k_trace_batch<<<256, 256, 0, qs>>>(d_fold, d_sys_list, d_counts + 3);
@@ -423,11 +499,17 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   if (mixed) QPR_HIP(enqueue_fold_judge(s));  // fold of delta = 0: renormalise + judge rho0
 
   auto enqueue_chunk = [&](hipStream_t qs) -> hipError_t {
-    for (int k = 0; k < o.chunk; ++k)
-      for (int q = 0; q < 4; ++q) {
+    for (int k = 0; k < o.chunk; ++k) {
+      for (int q = 0; q < (rkf ? 6 : 4); ++q) {
         hipError_t e = enqueue_stage(q, qs);
         if (e != hipSuccess) return e;
       }
+      if (rkf) {
+        k_commit_batch<<<grid_f, 256, 0, qs>>>(d_commit, d_items_f, d_counts + 2);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
     return mixed ? enqueue_fold_judge(qs) : hipSuccess;
   };
   hipGraph_t graph = nullptr;
@@ -504,6 +586,22 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     if (!stats) continue;
     qpr_stats& S = stats[k];
     S = qpr_stats{};
+    if (rkf) {
+      S.steps = f.accepted;
+      S.rejected = f.rejected;
+      S.rhs_evals = 6 * (f.accepted + f.rejected) + 1;
+      S.rhs_evals_fp64 = S.rhs_evals;
+      S.t = f.t;
+      S.last_step = f.h;
+      S.residual = std::sqrt(f.resid2);
+      S.trace_err = std::fabs(f.aux[0] - 1.0);
+      S.herm_err = f.aux[1];
+      S.min_diag = f.aux[2];
+      S.seconds = secs;
+      S.converged = f.converged;
+      S.status = f.nonfinite ? QPR_E_NONFINITE : f.converged ? QPR_OK : QPR_E_NOT_CONVERGED;
+      continue;
+    }
     S.steps = f.converged ? f.conv_step : f.step;
     S.folds = f.folds;
     S.rhs_evals_fp64 = mixed ? f.folds : 4 * S.steps + 1;

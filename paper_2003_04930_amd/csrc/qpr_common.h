@@ -148,8 +148,9 @@ struct EpiArgs {
 
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w,
                        const double* yr, const double* yi, int gate, hipStream_t s);
-hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w,
-                           hipStream_t s);
+// finish = false leaves a reducing stage's partials unfolded (kernel timing)
+hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
+                           bool finish = true);
 hipError_t launch_pad_in(const double* rho, int n, int ld, double* r, double* i,
                          double* p, hipStream_t s);
 hipError_t launch_pad_out(const double* r, const double* i, int n, int ld,
@@ -194,8 +195,17 @@ const char* batch_gemm_name(int cfg);
 int batch_gemm_tile(int cfg);
 hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,
                              const int* nitems, int grid, hipStream_t s);
+// finish: the stage reduces (stage 1, judge, Fehlberg stages 1 and 6), so the
+// finishing kernel folds each running system's partials (sys_list, nsys)
 hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* items,
-                                 const int* nitems, int grid, hipStream_t s);
+                                 const int* nitems, int grid, const int* sys_list,
+                                 const int* nsys, bool finish, hipStream_t s);
+// Fehlberg 4(5): epilogue arguments of stage st (0..5) on a workspace, and the
+// largest step whose fourth-order update is stable for the spectrum bound of
+// the Liouvillian at omega (rho_h = spectral radius of H).
+EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse);
+double rkf_step_cap(double omega, double rho_h);
+
 // variant: index into the sparse-product variants (-1 = pv.spmm_variant)
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
                        double* xi, const DevState* st, int gate, hipStream_t s, int variant = -1);

@@ -420,7 +420,7 @@ int gemm_default_cfg(int kind, int n) {
   // untuned defaults, from HIP-event sweeps on MI355X at N = 922, 2048, 4096:
   // small problems want more, smaller tiles; large ones 128-row tiles
   const bool big = ld >= 2048 && ld % 128 == 0;
-  if (kind == OP_F64) return big ? 2 : 1;
+  if (kind == OP_F64) return big ? 10 : 1;
   if (kind == OP_F32) return big ? 0 : 5;
   return big ? 3 : 0;
 }

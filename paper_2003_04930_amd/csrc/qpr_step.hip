@@ -51,12 +51,14 @@ __device__ __forceinline__ void split3(double v, uint16_t& s1, uint16_t& s2, uin
 }
 
 // Two-level reduction over the `nb` tiles of one system: every tile writes its
-// partials (sum, non-finite flag, max), takes a ticket, and the tile that
-// takes the last ticket combines all partials in index order (deterministic).
-__device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double my_max,
-                                               double* partials, DevState* st, double* red,
-                                               int* flag, double& tot, int& bad, double& mx,
-                                               int tile, int nb) {
+// partials (sum, non-finite flag, max) with plain stores, and a one-workgroup
+// finishing kernel launched after the tile kernel combines them in index
+// order (deterministic).  The kernel boundary makes the partials visible; a
+// last-tile ticket inside the tile kernel would need a device-scope release
+// fence per workgroup, which on this multi-XCD part writes back the XCD's L2
+// and serialises the workgroups.
+__device__ __forceinline__ void tile_partials(double my_sum, int my_bad, double my_max,
+                                              double* partials, double* red, int tile) {
   const int tid = threadIdx.x;
   double s = block_sum(my_sum, red, ETHREADS / 64);
   double m = block_max(my_max, red, ETHREADS / 64);
@@ -65,26 +67,21 @@ __device__ __forceinline__ void last_block_sum(double my_sum, int my_bad, double
     partials[3 * tile] = s;
     partials[3 * tile + 1] = (double)b;
     partials[3 * tile + 2] = m;
-    __threadfence();
-    const unsigned int t = atomicAdd(&st->ticket, 1u);
-    *flag = (t == (unsigned int)(nb - 1));
   }
-  __syncthreads();
-  tot = 0.0;
-  bad = 0;
-  mx = 0.0;
-  if (*flag) {
-    __threadfence();
-    double acc = 0.0, bb = 0.0, mm = 0.0;
-    for (int i = tid; i < nb; i += ETHREADS) {
-      acc += partials[3 * i];
-      bb = fmax(bb, partials[3 * i + 1]);
-      mm = fmax(mm, partials[3 * i + 2]);
-    }
-    tot = block_sum(acc, red, ETHREADS / 64);
-    mx = block_max(mm, red, ETHREADS / 64);
-    bad = __syncthreads_or(bb != 0.0);
+}
+
+__device__ __forceinline__ void reduce_partials(const double* partials, int nb, double* red,
+                                                double& tot, int& bad, double& mx) {
+  const int tid = threadIdx.x;
+  double acc = 0.0, bb = 0.0, mm = 0.0;
+  for (int i = tid; i < nb; i += ETHREADS) {
+    acc += partials[3 * i];
+    bb = fmax(bb, partials[3 * i + 1]);
+    mm = fmax(mm, partials[3 * i + 2]);
   }
+  tot = block_sum(acc, red, ETHREADS / 64);
+  mx = block_max(mm, red, ETHREADS / 64);
+  bad = __syncthreads_or(bb != 0.0);
 }
 
 // Tile pairs of the upper triangle: k -> (I, J), I <= J, column by column.
@@ -106,13 +103,11 @@ __host__ __device__ constexpr int tri_tiles(int t) { return t * (t + 1) / 2; }
 template <int XS>
 __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs& a,
                                               DevState* __restrict__ st,
-                                              double* __restrict__ partials, int tile,
-                                              int ntiles) {
+                                              double* __restrict__ partials, int tile) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
   __shared__ double Or[TE][TE + 1], Oi[TE][TE + 1];
   __shared__ double gs[TE];
   __shared__ double red[ETHREADS / 64];
-  __shared__ int flag;
   const int tid = threadIdx.x, tx = tid & (TE - 1), ty = tid / TE;
   const int n = pv.n, ld = pv.ld;
   int I, J;
@@ -351,79 +346,121 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
   }
 
-  if (a.mode == EPI_S1 || a.mode == EPI_RHS || fstage == 1 || fstage == 6) {
+  if (a.mode == EPI_S1 || a.mode == EPI_RHS || fstage == 1 || fstage == 6)
+    tile_partials(ssum, sbad, emax, partials, red, tile);
+}
+
+// Fehlberg stage number (1..6) of an epilogue mode, 0 for the others.
+__host__ __device__ __forceinline__ int fehlberg_stage(int mode) {
+  return mode >= EPI_F1 ? mode - EPI_F1 + 1 : 0;
+}
+
+// Whether an epilogue mode leaves partials for the finishing kernel.
+__host__ __device__ __forceinline__ bool reduces(int mode) {
+  const int f = fehlberg_stage(mode);
+  return mode == EPI_S1 || mode == EPI_RHS || f == 1 || f == 6;
+}
+
+// The control block's update from the combined reductions of one stage:
+// residual, convergence and step counting per check mode, or at the sixth
+// Fehlberg stage the step control.
+__device__ void finish_control(DevState* st, int check, int fstage, double tot, int bad,
+                               double mx) {
+  if (fstage == 6) {
+    // Fehlberg step control (Supplementary Note 2, Eq. (S13)): accept when
+    // |z - y| <= Tol h, next step h * (Tol h / (2 |z - y|))^(1/4), the factor
+    // clamped to [0.1, 4] and the step to h_max.
+    const double h = st->h, tolh = st->tol_step * h;
+    const int ok = !bad && mx <= tolh;
+    st->err = mx;
+    st->accept = ok;
+    if (ok) {
+      st->t += h;
+      st->accepted += 1;
+    } else {
+      st->rejected += 1;
+    }
+    if (bad) {
+      st->nonfinite = 1;
+      st->stop = 1;
+    }
+    double fac = mx > 0.0 ? pow(tolh / (2.0 * mx), 0.25) : 4.0;
+    fac = fmin(4.0, fmax(0.1, fac));
+    st->h = fmin(h * fac, st->h_max);
+    return;
+  }
+  st->resid2 = tot;
+  st->rhs_evals += 1;
+  if (bad) {
+    st->nonfinite = 1;
+    st->stop = 1;
+  } else if (check == CHK_PLAIN) {
+    if (tot < st->tol2) {
+      st->converged = 1;
+      st->conv_step = st->step;
+      st->stop = 1;
+    } else if (st->step >= st->max_steps) {
+      st->stop = 1;
+    } else {
+      st->step += 1;
+    }
+  } else if (check == CHK_DELTA) {
+    // ||r_a + L_lowp(delta)|| estimates the residual of rho_a + delta: once it
+    // meets 0.9 tol (or the step budget is spent) hold further steps so the
+    // FP64 fold and judge run.
+    if (tot < 0.81 * st->tol2 || st->step >= st->max_steps) st->hold = 1;
+    else st->step += 1;
+  } else if (check == CHK_RKF) {
+    if (tot < st->tol2) {
+      st->converged = 1;
+      st->conv_step = st->accepted;
+      st->stop = 1;
+    } else if (st->step >= st->max_steps) {
+      st->stop = 1;
+    } else {
+      st->step += 1;  // attempts
+    }
+  } else if (check == CHK_JUDGE) {
+    st->judge2 = tot;
+    st->folds += 1;
+    if (tot < st->tol2) {
+      st->converged = 1;
+      st->conv_step = st->step;
+      st->stop = 1;
+    } else if (st->step >= st->max_steps) {
+      st->stop = 1;
+    } else {
+      st->hold = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(ETHREADS)
+    k_finish(const double* __restrict__ partials, int nb, DevState* __restrict__ st, int check,
+             int fstage, int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  __shared__ double red[ETHREADS / 64];
+  double tot, mx;
+  int bad;
+  reduce_partials(partials, nb, red, tot, bad, mx);
+  if (threadIdx.x == 0) finish_control(st, check, fstage, tot, bad, mx);
+}
+
+// One workgroup per running system (grid-stride over the system list).
+__global__ void __launch_bounds__(ETHREADS)
+    k_finish_batch(const BatchEpi* __restrict__ args, const int* __restrict__ sys_list,
+                   const int* __restrict__ nsys) {
+  __shared__ double red[ETHREADS / 64];
+  const int ns = *nsys;
+  for (int it = blockIdx.x; it < ns; it += gridDim.x) {
+    const BatchEpi& e = args[sys_list[it]];
+    DevState* st = e.st;
+    if (st->stop || (e.a.gate && st->hold)) continue;
     double tot, mx;
     int bad;
-    last_block_sum(ssum, sbad, emax, partials, st, red, &flag, tot, bad, mx, tile, ntiles);
-    if (flag && tid == 0 && fstage == 6) {
-      // Fehlberg step control (Supplementary Note 2, Eq. (S13)): accept when
-      // |z - y| <= Tol h, next step h * (Tol h / (2 |z - y|))^(1/4), the factor
-      // clamped to [0.1, 4] and the step to h_max.
-      const double h = st->h, tolh = st->tol_step * h;
-      const int ok = !bad && mx <= tolh;
-      st->err = mx;
-      st->accept = ok;
-      if (ok) {
-        st->t += h;
-        st->accepted += 1;
-      } else {
-        st->rejected += 1;
-      }
-      if (bad) {
-        st->nonfinite = 1;
-        st->stop = 1;
-      }
-      double fac = mx > 0.0 ? pow(tolh / (2.0 * mx), 0.25) : 4.0;
-      fac = fmin(4.0, fmax(0.1, fac));
-      st->h = fmin(h * fac, st->h_max);
-      st->ticket = 0u;
-    } else if (flag && tid == 0) {
-      st->resid2 = tot;
-      st->rhs_evals += 1;
-      if (bad) {
-        st->nonfinite = 1;
-        st->stop = 1;
-      } else if (a.check == CHK_PLAIN) {
-        if (tot < st->tol2) {
-          st->converged = 1;
-          st->conv_step = st->step;
-          st->stop = 1;
-        } else if (st->step >= st->max_steps) {
-          st->stop = 1;
-        } else {
-          st->step += 1;
-        }
-      } else if (a.check == CHK_DELTA) {
-        // ||r_a + L_lowp(delta)|| estimates the residual of rho_a + delta:
-        // once it meets 0.9 tol (or the step budget is spent) hold further
-        // steps so the FP64 fold and judge run.
-        if (tot < 0.81 * st->tol2 || st->step >= st->max_steps) st->hold = 1;
-        else st->step += 1;
-      } else if (a.check == CHK_RKF) {
-        if (tot < st->tol2) {
-          st->converged = 1;
-          st->conv_step = st->accepted;
-          st->stop = 1;
-        } else if (st->step >= st->max_steps) {
-          st->stop = 1;
-        } else {
-          st->step += 1;  // attempts
-        }
-      } else if (a.check == CHK_JUDGE) {
-        st->judge2 = tot;
-        st->folds += 1;
-        if (tot < st->tol2) {
-          st->converged = 1;
-          st->conv_step = st->step;
-          st->stop = 1;
-        } else if (st->step >= st->max_steps) {
-          st->stop = 1;
-        } else {
-          st->hold = 0;
-        }
-      }
-      st->ticket = 0u;
-    }
+    reduce_partials(e.partials, tri_tiles(e.pv.ld / TE), red, tot, bad, mx);
+    if (threadIdx.x == 0) finish_control(st, e.a.check, fehlberg_stage(e.a.mode), tot, bad, mx);
+    __syncthreads();
   }
 }
 
@@ -431,12 +468,11 @@ template <int XS>
 __global__ void __launch_bounds__(ETHREADS)
     k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
   if (st->stop || (a.gate && st->hold)) return;
-  epilogue_tile<XS>(pv, a, st, partials, blockIdx.x, gridDim.x);
+  epilogue_tile<XS>(pv, a, st, partials, blockIdx.x);
 }
 
-// Persistent form for many systems (see k_gemm_k4_batch).  The tiles of one
-// system are counted by that system's own ticket, so its last tile folds its
-// own reduction regardless of which workgroups ran the others.
+// Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
+// its partials into its own system's buffer; k_finish_batch folds them.
 template <int XS>
 __global__ void __launch_bounds__(ETHREADS)
     k_epilogue_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
@@ -447,7 +483,7 @@ __global__ void __launch_bounds__(ETHREADS)
     const BatchEpi& e = args[item.x];
     DevState* st = e.st;
     if (st->stop || (e.a.gate && st->hold)) continue;
-    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y, tri_tiles(e.pv.ld / TE));
+    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y);
     __syncthreads();
   }
 }
@@ -912,7 +948,8 @@ ProbView view_of(const qpr_problem* P) {
                   P->h_ptr,    P->h_idx,    -1};
 }
 
-hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s) {
+hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
+                           bool finish) {
   const int grid = tri_tiles(pv.ld / TE);
   if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
   if (a.xkind == XS_DENSE64)
@@ -923,6 +960,8 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else
     return hipErrorInvalidValue;
+  if (finish && reduces(a.mode))
+    k_finish<<<1, ETHREADS, 0, s>>>(w.partials, grid, w.st, a.check, fehlberg_stage(a.mode), a.gate);
   return hipGetLastError();
 }
 
@@ -984,7 +1023,8 @@ hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int*
 }
 
 hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* items,
-                                 const int* nitems, int grid, hipStream_t s) {
+                                 const int* nitems, int grid, const int* sys_list,
+                                 const int* nsys, bool finish, hipStream_t s) {
   if (xsource == XS_DENSE64)
     k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else if (xsource == XS_DENSE32)
@@ -993,6 +1033,7 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
     k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else
     return hipErrorInvalidValue;
+  if (finish) k_finish_batch<<<256, ETHREADS, 0, s>>>(args, sys_list, nsys);
   return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ def lib():
         "qpr_autotune": (i32, [P, i32, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), vp,
                                sz, vp]),
         "qpr_load_tuning": (i32, [C.c_char_p]),
-        "qpr_batch_workspace_bytes": (sz, [i32, vp, i32]),
+        "qpr_batch_workspace_bytes": (sz, [i32, vp, i32, C.POINTER(qpr_opts)]),
         "qpr_batch_solve": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                   C.POINTER(qpr_opts), C.POINTER(i32), vp, sz, vp]),
         "qpr_product_config_name": (C.c_char_p, [i32, i32]),
@@ -495,13 +495,14 @@ class BatchResult:
 
 def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=None,
                 want_rank=True, chunk=32, use_graph=True, gemm_cfg=-1, product="auto",
-                allow_not_converged=False):
+                allow_not_converged=False, integrator="rk4", step_tol=1e-4, dt_max=0.0):
     """Solve [(Problem, omega), ...] together with qpr_batch_solve."""
     torch = _torch()
     import time as _time
     nsys = len(items)
     ns = (C.c_int32 * nsys)(*[P.n for P, _ in items])
-    nbytes = lib().qpr_batch_workspace_bytes(nsys, ns, PREC[prec])
+    op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product, integrator, step_tol, dt_max)
+    nbytes = lib().qpr_batch_workspace_bytes(nsys, ns, PREC[prec], C.byref(op))
     if nbytes == 0:
         raise QprError(QPR_E_ARG, "invalid batch request")
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -520,7 +521,6 @@ def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=N
     rho_ptrs = (C.c_void_p * nsys)(*[r.data_ptr() for r in rhos])
     rank_ptrs = (C.c_void_p * nsys)(*[(r.data_ptr() if r is not None else None) for r in ranks])
     stats = (qpr_stats * nsys)()
-    op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product)
     tuned = C.c_int32(-1)
     t0 = _time.perf_counter()
     status = lib().qpr_batch_solve(nsys, probs, omegas, float(dt), float(tol), int(max_steps),

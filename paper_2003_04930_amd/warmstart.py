@@ -140,6 +140,30 @@ def warm_rho0(P, omega, params, blend=True):
     return rho
 
 
+def warm_rho0_batch(items, params, blend=True):
+    """warm_rho0 for many (Problem, omega) pairs with one network pass."""
+    torch = _torch()
+    lams = [blend_weight(w) if blend else 1.0 for _, w in items]
+    need = [k for k, l in enumerate(lams) if l > 0.0]
+    preds = {}
+    if need:
+        B = Q.MpnnBatch([items[k] for k in need])
+        p = Q.mpnn_forward(B, params).to(torch.float64)
+        offs = B.graph_ptr.cpu().tolist()
+        for j, k in enumerate(need):
+            seg = p[offs[j]:offs[j + 1]]
+            preds[k] = seg / seg.sum()
+    out = []
+    for k, (P, _) in enumerate(items):
+        rho = torch.zeros((2, P.n, P.n), dtype=torch.float64, device="cuda")
+        if k in preds:
+            rho[0].diagonal().copy_(lams[k] * preds[k] + (1.0 - lams[k]) / P.n)
+        else:
+            rho[0].diagonal().fill_(1.0 / P.n)
+        out.append(rho)
+    return out
+
+
 def pagerank_rho0(P):
     """rho0 = diag(PageRank of G), the classical guess the network is compared with."""
     torch = _torch()

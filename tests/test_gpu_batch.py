@@ -45,6 +45,31 @@ def test_fp64_batch_equals_single_solves(Q, product):
         assert torch.equal(out.ranks[k], ref.rank)
 
 
+@pytest.mark.parametrize("product", ["sparse", "dense"])
+def test_rkf45_batch_equals_single_solves(Q, product):
+    """Each system keeps its own Fehlberg step size and control; the batched
+    kernels reproduce the single adaptive solves bit for bit."""
+    gs = small_family()[:4]
+    probs = [Q.Problem.from_graph(g) for g in gs]
+    items = [(P, w) for P in probs for w in (0.2, 0.9)]
+    out = Q.batch_solve(items, tol=1e-9, product=product, chunk=8, integrator="rkf45")
+    for k, (P, w) in enumerate(items):
+        ref = Q.steady_state(P, w, 0.01, 1e-9, 400000, product=product, integrator="rkf45")
+        st = out.stats[k]
+        assert st["converged"] == 1
+        assert st["steps"] == ref.stats["steps"] and st["rejected"] == ref.stats["rejected"]
+        assert st["last_step"] == ref.stats["last_step"]
+        assert torch.equal(out.rhos[k], ref.rho)
+        assert torch.equal(out.ranks[k], ref.rank)
+
+
+def test_rkf45_batch_rejects_low_precision(Q):
+    P = Q.Problem.from_graph(inputs.er_digraph(20, 0.2, seed=0))
+    with pytest.raises(Q.QprError) as e:
+        Q.batch_solve([(P, 0.5)], prec="fp32", integrator="rkf45")
+    assert e.value.status == Q.QPR_E_ARG
+
+
 def test_batch_graph_replay_equals_eager(Q):
     gs = small_family()[:3]
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.5,)]

@@ -122,3 +122,33 @@ def test_short_training_reduces_loss(Q):
     targets = warmstart.solve_targets(items, prec="bf16x3", tol=1e-6)
     params, hist = warmstart.train(items, targets, steps=150, batch_graphs=4, lr=3e-3, seed=0)
     assert hist[-1] < 0.5 * hist[0]
+
+
+def test_trained_weights_gain_over_identity_start(Q):
+    """The committed network (trained on 5000 steady states) against rho0 = I/N
+    on graphs it never saw: at omega = 0.9 the warm start needs fewer RK4 steps,
+    at omega = 0.2 the blended start is I/N itself (no loss), and every solve
+    still finishes at the FP64 tolerance at the same steady state."""
+    import os
+    from paper_2003_04930_amd import warmstart as W
+    path = os.path.join(os.path.dirname(W.__file__), "weights", "mpnn_warmstart.npy")
+    params = W.load(path)
+    assert params.numel() == Q.mpnn_param_count()
+    graphs = [inputs.ba_digraph(240, 3, seed=31337), inputs.er_digraph(300, 4.0 / 299, seed=4242)]
+    for g in graphs:
+        P = Q.Problem.from_graph(g)
+        for w in (0.9, 0.2):
+            cold = Q.steady_state(P, w, 0.01, 1e-8, 400000)
+            rho0 = W.warm_rho0(P, w, params)
+            warm = Q.steady_state(P, w, 0.01, 1e-8, 400000, rho0=rho0)
+            assert warm.stats["converged"] == 1
+            assert float((warm.rho - cold.rho).abs().max()) < 1e-6
+            if w == 0.9:
+                assert warm.stats["steps"] < cold.stats["steps"], (g, w)
+            else:
+                assert warm.stats["steps"] == cold.stats["steps"]
+    # one batched network pass gives the same start states
+    items = [(Q.Problem.from_graph(g), w) for g in graphs for w in (0.9, 0.55)]
+    many = W.warm_rho0_batch(items, params)
+    for (P, w), r in zip(items, many):
+        assert torch.allclose(r, W.warm_rho0(P, w, params), rtol=0, atol=1e-9)
