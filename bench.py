@@ -97,6 +97,9 @@ def tie_aware_rank_check(p_ref, rank, tau, np):
 
 def accelerated(Q, W, P, params, plain, plain_value, torch, np):
     """RKF45 from the omega-blended learned warm start (inference included)."""
+    for w in OMEGAS:  # untimed: first use of the network path (allocations)
+        W.warm_rho0(P, w, params)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = []
     for w in OMEGAS:

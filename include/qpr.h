@@ -154,7 +154,9 @@ typedef enum {
                     first step; the two 4101 denominators read as 4104; FP64 */
 } qpr_integrator;
 
-/* How the commutator product X = H_off rho is formed. */
+/* How the commutator product X = H_off rho is formed.  The sparse product
+ * serves QPR_FP64 (FP64 operand) and QPR_FP32 (gathers of the FP32 copy of
+ * the state, sums in FP64, X rounded to FP32); QPR_BF16X3 is always dense. */
 typedef enum {
   QPR_PRODUCT_AUTO = 0,   /* sparse when H_off is below 5 % dense, else dense */
   QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
@@ -338,8 +340,9 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * `reps` classical RK4 steps (stages 1-4 in turn, stage 1 with its residual,
  * trace and finiteness reductions; X held fixed; each reads Y_s, y_n and the
  * accumulator, writes the accumulator and Y_{s+1}, plus X
- * for the dense product).  cfg = -2 with QPR_FP64 times the sparse product
- * (CSR gathers of rho through the pattern of H_off) in place of the dense one;
+ * for the dense product).  cfg = -2 with QPR_FP64 or QPR_FP32 times the
+ * sparse product (CSR gathers of rho through the pattern of H_off) in place
+ * of the dense one;
  * cfg = -3 - v times sparse-product variant v: 0 cm_w32_r1, 1 cm_w64_r1,
  * 2 cm_w128_r1, 3 cm_w64_r2 (column-chunk major, XCD-aware: W columns of
  * both planes per wave, R rows per wave), 4 row128 (one workgroup per row and

@@ -236,13 +236,14 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
 
   const bool mixed = prec == QPR_FP32;
   const int xk = mixed ? OP_F32 : OP_F64;
-  // products: FP64 steps and all judges may gather sparsely; FP32 steps are dense MFMA
+  // products: sparse gathers (FP64 operands, or the FP32 delta copy in FP32
+  // mode) below 5 % density unless opts->product says otherwise
   auto sparse_for = [&](const qpr_problem* P) {
     if (o.product == QPR_PRODUCT_DENSE) return false;
     if (o.product == QPR_PRODUCT_SPARSE) return true;
     return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
   };
-  const bool step_sparse = !mixed && sparse_for(probs[0]);
+  const bool step_sparse = sparse_for(probs[0]);
   const bool judge_sparse = sparse_for(probs[0]);
 
   // host argument tables: slots 0..3 = RK4 stages, 4 = judge / RHS; or the six
@@ -425,7 +426,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     return e;
   };
 
-  const bool use_gemm = mixed || !step_sparse;
+  const bool use_gemm = !step_sparse;
   const int grid_g = 1024, grid_e = 2048, grid_f = 1024;
   // tile configuration: tuned on this batch's own work list unless given
   int cands[8];
@@ -472,7 +473,9 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     const bool gemm = judge ? !judge_sparse : use_gemm;
     const bool spmm = judge ? judge_sparse : step_sparse;
     if (spmm) {
-      e = launch_spmm_batch(d_epi + (size_t)q * nsys, d_items_s, d_counts + 4, grid_e, qs);
+      e = mixed && !judge
+              ? launch_spmm_f32_batch(d_epi + (size_t)q * nsys, d_items_s, d_counts + 4, grid_e, qs)
+              : launch_spmm_batch(d_epi + (size_t)q * nsys, d_items_s, d_counts + 4, grid_e, qs);
       if (e != hipSuccess) return e;
     }
     if (gemm) {

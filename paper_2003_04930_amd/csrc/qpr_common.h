@@ -209,12 +209,18 @@ double rkf_step_cap(double omega, double rho_h);
 // variant: index into the sparse-product variants (-1 = pv.spmm_variant)
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
                        double* xi, const DevState* st, int gate, hipStream_t s, int variant = -1);
+// FP32 operand form (mixed-precision steps): X (FP32) = H_off Y (FP32 copy)
+hipError_t launch_spmm_f32(const ProbView& pv, const float* yr, const float* yi, float* xr,
+                           float* xi, const DevState* st, int gate, hipStream_t s);
 int spmm_num_variants();
 const char* spmm_variant_name(int v);
 int spmm_items_per_system(int n, int ld);
 int epilogue_items_per_system(int ld);
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
                              hipStream_t s);
+// FP32 operand form over the same items: a.lor / a.loi -> a.xfr / a.xfi
+hipError_t launch_spmm_f32_batch(const BatchEpi* args, const int2* items, const int* nitems,
+                                 int grid, hipStream_t s);
 
 int gemm_num_cfgs(int kind);
 const char* gemm_cfg_name(int kind, int cfg);

@@ -42,8 +42,10 @@ qpr_status fail(qpr_status s, const char* fmt, ...) {
 void clear_error() { g_err[0] = 0; }
 
 // Sparse gathers for the FP64 product when H_off is sparse enough (or forced).
+// The sparse product serves the FP64 and the FP32-operand products (there is
+// no three-slice bf16 form: its point is the MFMA throughput of dense tiles).
 static bool use_sparse(const qpr_problem* P, int product, int xk) {
-  if (xk != OP_F64 || product == QPR_PRODUCT_DENSE) return false;
+  if (xk == OP_BF16X3 || product == QPR_PRODUCT_DENSE) return false;
   if (product == QPR_PRODUCT_SPARSE) return true;
   return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
 }
@@ -55,6 +57,16 @@ static qpr_status view_for(const qpr_problem* P, const qpr_opts& o, ProbView* pv
     return fail(QPR_E_ARG, "sparse_variant must be in [0, %d]", spmm_num_variants());
   pv->spmm_variant = o.sparse_variant - 1;
   return QPR_OK;
+}
+
+// X = H_off Y for a stage: the sparse gathers (FP64 operand, or the FP32 copy
+// of the state in FP32 mode) or the dense MFMA product.
+static hipError_t launch_product(const qpr_problem* P, const Ws& w, const ProbView& pv, int xk,
+                                 int cfg, bool sparse, const double* yr, const double* yi,
+                                 int gate, hipStream_t s, int spv = -1) {
+  if (!sparse) return launch_gemm(xk, cfg, P, w, yr, yi, gate, s);
+  if (xk == OP_F32) return launch_spmm_f32(pv, w.lo_r, w.lo_i, w.xf_r, w.xf_i, w.st, gate, s);
+  return launch_spmm(pv, yr, yi, w.x_r, w.x_i, w.st, gate, s, spv);
 }
 
 static int op_kind(int prec) {
@@ -234,7 +246,7 @@ static EpiArgs rk4_stage_args(const Ws& w, int k, double omega, double dt, int x
   a.omega = omega;
   a.cdt = sg.cdt;
   a.mode = EPI_S1 + k;
-  a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
+  a.xkind = xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
   a.check = k == 0 ? check : CHK_NONE;
   a.gate = gate;
   return a;
@@ -247,8 +259,7 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
   const bool sparse = use_sparse(P, product, xk);
   for (int k = 0; k < 4; ++k) {
     const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, sparse, check, gate, with_ra);
-    hipError_t e = sparse ? launch_spmm(pv, a.ysr, a.ysi, w.x_r, w.x_i, w.st, gate, s)
-                          : launch_gemm(xk, cfg, P, w, a.ysr, a.ysi, gate, s);
+    hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, a.ysr, a.ysi, gate, s);
     if (e != hipSuccess) return e;
     e = launch_epilogue(pv, a, w, s);
     if (e != hipSuccess) return e;
@@ -266,8 +277,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
     if (e != hipSuccess) return e;
   }
   {
-    hipError_t e = sparse ? launch_spmm(pv, inr, ini, w.x_r, w.x_i, w.st, 0, s)
-                          : launch_gemm(xk, cfg, P, w, inr, ini, 0, s);
+    hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, inr, ini, 0, s);
     if (e != hipSuccess) return e;
   }
   EpiArgs a{};
@@ -282,7 +292,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
   a.outi = outi;
   a.omega = omega;
   a.mode = EPI_RHS;
-  a.xkind = sparse ? XS_SPARSE64 : xk == OP_F64 ? XS_DENSE64 : XS_DENSE32;
+  a.xkind = xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
   a.check = check;
   return launch_epilogue(pv, a, w, s);
 }
@@ -723,14 +733,13 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   QPR_HIP(launch_fill(w.acc_r, 2 * (size_t)P->ld * P->ld * 8, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
   // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v
-  const bool sparse = cfg <= -2 && xk == OP_F64;
+  const bool sparse = cfg <= -2 && xk != OP_BF16X3;
   const int spv = cfg <= -3 ? -3 - cfg : -1;
   if (sparse && spv >= spmm_num_variants()) return fail(QPR_E_ARG, "no such sparse-product variant");
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   for (auto& e : ev) QPR_HIP(hipEventCreate(&e));
   auto product = [&]() {
-    return sparse ? launch_spmm(pv, w.y1_r, w.y1_i, w.x_r, w.x_i, w.st, 0, s, spv)
-                  : launch_gemm(xk, cfg, P, w, w.y1_r, w.y1_i, 0, s);
+    return launch_product(P, w, pv, xk, cfg, sparse, w.y1_r, w.y1_i, 0, s, spv);
   };
   for (int r = 0; r < 3; ++r) QPR_HIP(product());
   QPR_HIP(hipEventRecord(ev[0], s));

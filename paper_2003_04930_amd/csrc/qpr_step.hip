@@ -520,9 +520,9 @@ constexpr int SP_WAVES = 4;
 // either predicated (PRED: eight loads, the missing ones repeating the last
 // neighbour and masked out) or taken one guarded load at a time (no extra
 // requests; better where the memory system rather than latency is the limit).
-template <int S, bool PRED>
+template <int S, bool PRED, typename T = double>
 __device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e0, int e1, int ld,
-                                            const double* const (&base)[S], double (&out)[S]) {
+                                            const T* const (&base)[S], double (&out)[S]) {
   double acc[8][S];
 #pragma unroll
   for (int k = 0; k < 8; ++k)
@@ -537,7 +537,7 @@ __device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll
-      for (int q = 0; q < S; ++q) v[k][q] = base[q][off[k]];
+      for (int q = 0; q < S; ++q) v[k][q] = (double)base[q][off[k]];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -552,7 +552,7 @@ __device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e
 #pragma unroll
       for (int k = 0; k < 8; ++k)
 #pragma unroll
-        for (int q = 0; q < S; ++q) v[k][q] = base[q][off[k]];
+        for (int q = 0; q < S; ++q) v[k][q] = (double)base[q][off[k]];
 #pragma unroll
       for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -563,7 +563,7 @@ __device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e
         if (e + k < e1) {
           const size_t o = (size_t)h_idx[e + k] * ld;
 #pragma unroll
-          for (int q = 0; q < S; ++q) acc[k][q] += base[q][o];
+          for (int q = 0; q < S; ++q) acc[k][q] += (double)base[q][o];
         }
     }
   }
@@ -659,6 +659,79 @@ __global__ void __launch_bounds__(2 * SP_COLS)
   double o[1];
   gather_rows<1, false>(pv.h_idx, pv.h_ptr[a], pv.h_ptr[a + 1], pv.ld, b, o);
   (t < SP_COLS ? xr : xi)[(size_t)a * pv.ld + c] = (double)pv.hsign * o[0];
+}
+
+// FP32 operand form for the mixed-precision steps: the gathered rows are the
+// FP32 copy of the stage state (the defect delta), summed in FP64 in the order
+// above and rounded once to FP32 for X.  Column chunks as in the FP64
+// chunk-major variants: W = 32 (lanes 0-31 real plane, 32-63 imaginary),
+// W = 64 (lane l: column l of both planes), W = 128 (lane l: columns 2l,
+// 2l+1 of both planes).
+template <int W>
+__device__ __forceinline__ void spmm_f32_row(const ProbView& pv, const float* __restrict__ yr,
+                                             const float* __restrict__ yi,
+                                             float* __restrict__ xr, float* __restrict__ xi,
+                                             int a, int chunk) {
+  const int l = threadIdx.x & 63, ld = pv.ld;
+  const int e0 = pv.h_ptr[a], e1 = pv.h_ptr[a + 1];
+  const double sg = (double)pv.hsign;
+  const size_t row = (size_t)a * ld;
+  if (W == 32) {
+    const int c = chunk * 32 + (l & 31);
+    const float* const b[1] = {(l < 32 ? yr : yi) + c};
+    double o[1];
+    gather_rows<1, true, float>(pv.h_idx, e0, e1, ld, b, o);
+    (l < 32 ? xr : xi)[row + c] = (float)(sg * o[0]);
+  } else if (W == 64) {
+    const int c = chunk * 64 + l;
+    const float* const b[2] = {yr + c, yi + c};
+    double o[2];
+    gather_rows<2, true, float>(pv.h_idx, e0, e1, ld, b, o);
+    xr[row + c] = (float)(sg * o[0]);
+    xi[row + c] = (float)(sg * o[1]);
+  } else {
+    const int c = chunk * 128 + 2 * l;
+    const float* const b[4] = {yr + c, yr + c + 1, yi + c, yi + c + 1};
+    double o[4];
+    gather_rows<4, true, float>(pv.h_idx, e0, e1, ld, b, o);
+    *(float2*)(xr + row + c) = make_float2((float)(sg * o[0]), (float)(sg * o[1]));
+    *(float2*)(xi + row + c) = make_float2((float)(sg * o[2]), (float)(sg * o[3]));
+  }
+}
+
+// one logical workgroup (chunk, group of four rows) of the FP32 form
+template <int W>
+__device__ __forceinline__ void spmm_f32_group(const ProbView& pv, const float* yr,
+                                               const float* yi, float* xr, float* xi,
+                                               int logical) {
+  const int groups = spmm_cm_groups<1>(pv.n);
+  const int chunk = logical / groups, g = logical - chunk * groups;
+  const int a = g * SP_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (a < pv.n) spmm_f32_row<W>(pv, yr, yi, xr, xi, a, chunk);
+}
+
+template <int W>
+__global__ void __launch_bounds__(64 * SP_WAVES)
+    k_spmm_f32(ProbView pv, const float* __restrict__ yr, const float* __restrict__ yi,
+               float* __restrict__ xr, float* __restrict__ xi, const DevState* __restrict__ st,
+               int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  spmm_f32_group<W>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Persistent FP32 form over the (system, chunk * groups + group) items of the
+// 32-column chunking; operand = the system's FP32 state copy (a.lor), result
+// into its FP32 product planes (a.xfr).
+__global__ void __launch_bounds__(64 * SP_WAVES)
+    k_spmm_f32_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
+                     const int* __restrict__ nitems) {
+  const int ni = *nitems;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int2 item = items[it];
+    const BatchEpi& e = args[item.x];
+    if (e.st->stop || (e.a.gate && e.st->hold)) continue;
+    spmm_f32_group<32>(e.pv, e.a.lor, e.a.loi, (float*)e.a.xfr, (float*)e.a.xfi, item.y);
+  }
 }
 
 // Persistent form over (system, chunk * groups + group) items of the W = 32,
@@ -1009,6 +1082,22 @@ hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, d
     grid = (pv.ld / v.cols) * groups;
     v.fn<<<grid, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_f32_batch(const BatchEpi* args, const int2* items, const int* nitems,
+                                 int grid, hipStream_t s) {
+  k_spmm_f32_batch<<<grid, 64 * SP_WAVES, 0, s>>>(args, items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_f32(const ProbView& pv, const float* yr, const float* yi, float* xr,
+                           float* xi, const DevState* st, int gate, hipStream_t s) {
+  const int groups = (pv.n + SP_WAVES - 1) / SP_WAVES;
+  if (pv.ld % 128 == 0)
+    k_spmm_f32<128><<<(pv.ld / 128) * groups, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+  else
+    k_spmm_f32<64><<<(pv.ld / 64) * groups, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
   return hipGetLastError();
 }
 

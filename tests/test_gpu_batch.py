@@ -79,11 +79,13 @@ def test_batch_graph_replay_equals_eager(Q):
         assert torch.equal(x, y)
 
 
-def test_fp32_batch_meets_fp64_judge_and_oracle(Q):
+@pytest.mark.parametrize("product", ["sparse", "dense"])
+def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product):
     gs = small_family()
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.1, 0.9)]
-    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32)
-    assert out.tuned_cfg >= 0
+    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32, product=product)
+    # the dense FP32 product is tuned on the batch; the sparse one has no tiles
+    assert (out.tuned_cfg >= 0) == (product == "dense")
     for k, ((P, w), g) in enumerate(zip(items, [g for g in gs for _ in (0.1, 0.9)])):
         st = out.stats[k]
         assert st["converged"] == 1 and st["folds"] >= 1

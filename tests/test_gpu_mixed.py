@@ -2,7 +2,8 @@
 correction, against the CPU FP64 oracle.
 
 Bounds: a low-precision product row sums at most deg(a) terms of the FP32
-(or 3-slice bf16, 24-bit) representation of rho with FP32 accumulation, so
+(or 3-slice bf16, 24-bit) representation of rho with FP32 (dense MFMA) or FP64
+(sparse gathers, rounded once to FP32) accumulation, so
 |X_lowp - X| <= c * 2^-24 * deg_max * max|rho|; the right-hand side inherits
 that times (1 - omega).  The steady state is judged by the FP64 residual, so
 the mixed solution must satisfy ||L(rho)||_F < tol re-measured by the oracle
@@ -26,14 +27,14 @@ def Q():
     return qpr
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
 @pytest.mark.parametrize("n,m,omega", [(70, 2, 0.3), (130, 3, 0.8), (922, 3, 0.5)])
-def test_lowp_rhs_error_bound(Q, prec, n, m, omega):
+def test_lowp_rhs_error_bound(Q, prec, product, n, m, omega):
     g = inputs.ba_digraph(n, m, seed=n)
     P = Q.Problem.from_graph(g)
     R = O.problem_ref(g.n, g.src, g.dst)
     rho = inputs.random_density(n, seed=3)
-    got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho), prec=prec))
+    got = Q.to_complex(Q.rhs(P, omega, Q.planar(rho), prec=prec, product=product))
     want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, omega)
     deg = int((R.H != 0).sum(axis=1).max())
     bound = 8 * 2.0 ** -24 * (deg + 1) * np.max(np.abs(rho)) * (1 - omega) + 1e-15
@@ -43,15 +44,16 @@ def test_lowp_rhs_error_bound(Q, prec, n, m, omega):
     assert np.array_equal(got, got.conj().T)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_steady_state_matches_oracle(Q, prec):
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
+def test_mixed_steady_state_matches_oracle(Q, prec, product):
     g = inputs.ba_digraph(130, 3, seed=1)
     P = Q.Problem.from_graph(g)
     R = O.problem_ref(g.n, g.src, g.dst)
     omega, dt, tol = 0.6, 0.01, 1e-9
     f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, omega)
     want, nsteps, _ = O.steady_ref(np.eye(g.n) / g.n, f, dt, tol, 200000)
-    out = Q.steady_state(P, omega, dt, tol, 200000, prec=prec, chunk=32, fold_every=32)
+    out = Q.steady_state(P, omega, dt, tol, 200000, prec=prec, chunk=32, fold_every=32,
+                         product=product)
     got = Q.to_complex(out.rho)
     assert out.stats["converged"] == 1
     assert out.stats["folds"] >= 2
@@ -72,13 +74,13 @@ def test_mixed_steady_state_matches_oracle(Q, prec):
                 assert pos[i] < pos[j]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_n922_against_fp64_gpu(Q, prec):
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
+def test_mixed_n922_against_fp64_gpu(Q, prec, product):
     g = inputs.ba_digraph(922, 3, seed=0)
     P = Q.Problem.from_graph(g)
     R = O.problem_ref(g.n, g.src, g.dst)
     ref = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000)
-    out = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000, prec=prec)
+    out = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000, prec=prec, product=product)
     a, b = Q.to_complex(out.rho), Q.to_complex(ref.rho)
     assert np.max(np.abs(a - b)) < 1e-6
     res = np.sqrt(np.sum(np.abs(O.rhs_ref(a, R.H_sparse, R.G, R.d, 0.8)) ** 2))
@@ -91,8 +93,8 @@ def test_lowp_rk4_trajectory_close_to_fp64(Q):
     rho0 = inputs.random_density(200, seed=9)
     x64 = Q.planar(rho0)
     Q.rk4_step(P, 0.5, 0.01, 30, x64)
-    for prec in ("fp32", "bf16x3"):
+    for prec, product in (("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")):
         x = Q.planar(rho0)
-        Q.rk4_step(P, 0.5, 0.01, 30, x, prec=prec)
+        Q.rk4_step(P, 0.5, 0.01, 30, x, prec=prec, product=product)
         err = (x - x64).abs().max().item()
         assert 0 < err < 1e-7
