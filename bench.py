@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--no-4096", action="store_true", help="skip the N = 4096 rows")
     ap.add_argument("--batch-graphs", type=int, default=0,
                     help="also time qpr_batch_solve on this many family graphs x 5 omegas")
+    ap.add_argument("--batch-rows", default="fp64,fp64_rkf45,fp64_rkf45_warm,fp32",
+                    help="comma list of batched rows to time")
     ap.add_argument("--precision-n", type=int, default=0,
                     help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
     ap.add_argument("--warm", default=WEIGHTS,
@@ -265,7 +267,7 @@ def main():
              "nnz_h": int(P.p.nnz_h), "ld": ld}
 
     params = None
-    if args.warm and args.warm != "none" and not args.no_rkf45:
+    if args.warm and args.warm != "none":
         from paper_2003_04930_amd import warmstart as W
         params = W.load(args.warm)
 
@@ -328,7 +330,10 @@ def main():
             runs.append(("fp64_rkf45_warm", dict(prec="fp64", integrator="rkf45", warm=True)))
         if not args.no_mixed:
             runs.append(("fp32", dict(prec="fp32")))
+        wanted = set(args.batch_rows.split(","))
         for name, kw in runs:
+            if name not in wanted:
+                continue
             rho0s = None
             t_inf = 0.0
             if kw.pop("warm", False):

@@ -28,7 +28,10 @@ namespace qpr {
 namespace {
 
 constexpr int TE = 32;       // epilogue tile edge
-constexpr int ETHREADS = 256;
+constexpr int ETHREADS = 512;
+constexpr int ERS = ETHREADS / TE;  // tile rows covered per pass of the workgroup
+constexpr int EM = TE / ERS;        // tile elements per thread
+static_assert(ETHREADS % TE == 0 && TE % ERS == 0, "epilogue thread layout");
 
 __device__ __forceinline__ uint16_t bf16_rn(float f) {
   // round-to-nearest-even float -> bf16 (inputs are finite here)
@@ -117,8 +120,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
 #pragma unroll
-  for (int m = 0; m < TE / 8; ++m) {
-    const int r = ty + 8 * m;
+  for (int m = 0; m < EM; ++m) {
+    const int r = ty + ERS * m;
     const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
     if (XS != XS_DENSE32) {
       Tr[r][tx] = a.xr[o];
@@ -137,35 +140,35 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     }
     const double P = block_sum(sp, red, ETHREADS / 64);
     const double D = block_sum(sd, red, ETHREADS / 64);
-    // eight lanes per row, all 32 rows at once: lane k of a row takes in-links
-    // k, k + 8, ... (four in flight), then a reduction over the eight lanes in
+    // GL lanes per row, all 32 rows at once: lane k of a row takes in-links
+    // k, k + GL, ... (four in flight), then a reduction over the GL lanes in
     // a fixed order.  The row sums are the critical path of a diagonal tile.
     GainView gv{n, pv.teleport, pv.alpha, pv.inv_outdeg, pv.dangling, pv.in_ptr, pv.in_idx};
-    static_assert(ETHREADS == 8 * TE, "eight lanes per row of the tile");
-    const int q = tid >> 3, k = tid & 7;
+    constexpr int GL = ETHREADS / TE;
+    static_assert(GL <= 64 && (GL & (GL - 1)) == 0, "lanes of a row share a wave");
+    const int q = tid / GL, k = tid % GL;
     const int ar = a0 + q;
     double sacc = 0.0;
     if (ar < n) {
       const int e1 = pv.in_ptr[ar + 1];
       int e = pv.in_ptr[ar] + k;
       double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-      for (; e + 24 < e1; e += 32) {
-        const int j0 = pv.in_idx[e], j1 = pv.in_idx[e + 8], j2 = pv.in_idx[e + 16],
-                  j3 = pv.in_idx[e + 24];
+      for (; e + 3 * GL < e1; e += 4 * GL) {
+        const int j0 = pv.in_idx[e], j1 = pv.in_idx[e + GL], j2 = pv.in_idx[e + 2 * GL],
+                  j3 = pv.in_idx[e + 3 * GL];
         t0 += a.ps[j0] * pv.inv_outdeg[j0];
         t1 += a.ps[j1] * pv.inv_outdeg[j1];
         t2 += a.ps[j2] * pv.inv_outdeg[j2];
         t3 += a.ps[j3] * pv.inv_outdeg[j3];
       }
-      for (; e < e1; e += 8) {
+      for (; e < e1; e += GL) {
         const int j = pv.in_idx[e];
         t0 += a.ps[j] * pv.inv_outdeg[j];
       }
       sacc = (t0 + t1) + (t2 + t3);
     }
-    sacc += __shfl_xor(sacc, 1, 64);
-    sacc += __shfl_xor(sacc, 2, 64);
-    sacc += __shfl_xor(sacc, 4, 64);
+#pragma unroll
+    for (int off = 1; off < GL; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
     if (k == 0 && ar < n) gs[q] = gain_finish(gv, ar, a.ps, P, D, sacc);
   }
   __syncthreads();
@@ -181,13 +184,12 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   // All loads of this thread's four elements are issued before any store:
   // outputs may alias inputs (y_n is updated in place at the last RK4 stage),
   // so the compiler could not reorder them across the stores itself.
-  constexpr int EM = TE / 8;
   const bool need_yn = a.mode != EPI_RHS;
   const bool need_acc = a.mode == EPI_S2 || a.mode == EPI_S3 || a.mode == EPI_S4;
   double xa[EM], xb[EM], yr_[EM], yi_[EM], nr_[EM], ni_[EM], cr_[EM], ci_[EM], rr_[EM], ri_[EM];
 #pragma unroll
   for (int m = 0; m < EM; ++m) {
-    const int ar = a0 + ty + 8 * m;
+    const int ar = a0 + ty + ERS * m;
     const size_t o = (size_t)ar * ld + b;
     xa[m] = xb[m] = yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
     if (bin && ar < n) {
@@ -216,7 +218,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   }
 #pragma unroll
   for (int m = 0; m < EM; ++m) {
-    const int r = ty + 8 * m;
+    const int r = ty + ERS * m;
     const int ar = a0 + r;
     const size_t o = (size_t)ar * ld + b;
     double kr = 0.0, ki = 0.0;
@@ -321,8 +323,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     // mirror tile (J, I) = conj of tile (I, J), written row-major through LDS
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < TE / 8; ++m) {
-      const int r = ty + 8 * m;
+    for (int m = 0; m < EM; ++m) {
+      const int r = ty + ERS * m;
       const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
       const double outr = Or[tx][r], outi = -Oi[tx][r];
       a.outr[o] = outr;
@@ -464,8 +466,10 @@ __global__ void __launch_bounds__(ETHREADS)
   }
 }
 
+// six waves per SIMD (<= 80 VGPRs, no spills): three 512-thread workgroups
+// per CU instead of two at the unconstrained 88 VGPRs
 template <int XS>
-__global__ void __launch_bounds__(ETHREADS)
+__global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
   if (st->stop || (a.gate && st->hold)) return;
   epilogue_tile<XS>(pv, a, st, partials, blockIdx.x);
