@@ -109,6 +109,16 @@ struct ProbView {
 };
 ProbView view_of(const qpr_problem* P);
 
+// The finishing step of a reducing stage (fold the tile partials, update the
+// control block), run by k_finish or by one extra workgroup of the next
+// sparse-product launch.  nb = 0: nothing to finish.
+struct FinishJob {
+  const double* partials;
+  int nb;
+  DevState* st;
+  int check, fstage, gate;
+};
+
 // Epilogue modes: the right-hand side alone, the four classical RK4 stages,
 // and the six Fehlberg 4(5) stages (EPI_F1 + s - 1 for stage s).
 enum EpiMode { EPI_RHS = 0, EPI_S1 = 1, EPI_S2 = 2, EPI_S3 = 3, EPI_S4 = 4, EPI_F1 = 11 };
@@ -206,12 +216,17 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
 EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse);
 double rkf_step_cap(double omega, double rho_h);
 
-// variant: index into the sparse-product variants (-1 = pv.spmm_variant)
+// variant: index into the sparse-product variants (-1 = pv.spmm_variant);
+// fin: the finishing step of the previous stage, run by one extra workgroup
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
-                       double* xi, const DevState* st, int gate, hipStream_t s, int variant = -1);
+                       double* xi, const DevState* st, int gate, hipStream_t s, int variant = -1,
+                       const FinishJob* fin = nullptr);
 // FP32 operand form (mixed-precision steps): X (FP32) = H_off Y (FP32 copy)
 hipError_t launch_spmm_f32(const ProbView& pv, const float* yr, const float* yi, float* xr,
-                           float* xi, const DevState* st, int gate, hipStream_t s);
+                           float* xi, const DevState* st, int gate, hipStream_t s,
+                           const FinishJob* fin = nullptr);
+// The finishing step of a reducing epilogue launch with these arguments.
+FinishJob finish_job(const ProbView& pv, const EpiArgs& a, const Ws& w);
 int spmm_num_variants();
 const char* spmm_variant_name(int v);
 int spmm_items_per_system(int n, int ld);

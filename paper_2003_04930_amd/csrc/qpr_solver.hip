@@ -61,12 +61,14 @@ static qpr_status view_for(const qpr_problem* P, const qpr_opts& o, ProbView* pv
 
 // X = H_off Y for a stage: the sparse gathers (FP64 operand, or the FP32 copy
 // of the state in FP32 mode) or the dense MFMA product.
+// A sparse launch may carry the finishing step `fin` of the previous stage.
 static hipError_t launch_product(const qpr_problem* P, const Ws& w, const ProbView& pv, int xk,
                                  int cfg, bool sparse, const double* yr, const double* yi,
-                                 int gate, hipStream_t s, int spv = -1) {
+                                 int gate, hipStream_t s, int spv = -1,
+                                 const FinishJob* fin = nullptr) {
   if (!sparse) return launch_gemm(xk, cfg, P, w, yr, yi, gate, s);
-  if (xk == OP_F32) return launch_spmm_f32(pv, w.lo_r, w.lo_i, w.xf_r, w.xf_i, w.st, gate, s);
-  return launch_spmm(pv, yr, yi, w.x_r, w.x_i, w.st, gate, s, spv);
+  if (xk == OP_F32) return launch_spmm_f32(pv, w.lo_r, w.lo_i, w.xf_r, w.xf_i, w.st, gate, s, fin);
+  return launch_spmm(pv, yr, yi, w.x_r, w.x_i, w.st, gate, s, spv, fin);
 }
 
 static int op_kind(int prec) {
@@ -257,12 +259,17 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
                                hipStream_t s) {
   const int gate = check == CHK_DELTA ? 1 : 0;
   const bool sparse = use_sparse(P, product, xk);
+  // with the sparse product the stage-2 launch carries stage 1's finishing step
+  FinishJob pending{};
   for (int k = 0; k < 4; ++k) {
     const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, sparse, check, gate, with_ra);
-    hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, a.ysr, a.ysi, gate, s);
+    hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, a.ysr, a.ysi, gate, s, -1,
+                                  k == 1 ? &pending : nullptr);
     if (e != hipSuccess) return e;
-    e = launch_epilogue(pv, a, w, s);
+    const bool carry = sparse && k == 0;
+    e = launch_epilogue(pv, a, w, s, !carry);
     if (e != hipSuccess) return e;
+    if (carry) pending = finish_job(pv, a, w);
   }
   return hipSuccess;
 }
@@ -391,13 +398,16 @@ EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse) {
 static hipError_t enqueue_rkf_attempt(const qpr_problem* P, const Ws& w, const ProbView& pv,
                                       double omega, int cfg, int product, hipStream_t s) {
   const bool sparse = use_sparse(P, product, OP_F64);
+  FinishJob pending{};  // stage 1's finishing step rides on the stage-2 sparse launch
   for (int st = 0; st < 6; ++st) {
     const EpiArgs a = rkf_stage_args(w, st, omega, sparse);
-    hipError_t e = sparse ? launch_spmm(pv, a.ysr, a.ysi, w.x_r, w.x_i, w.st, 0, s)
-                          : launch_gemm(OP_F64, cfg, P, w, a.ysr, a.ysi, 0, s);
+    hipError_t e = launch_product(P, w, pv, OP_F64, cfg, sparse, a.ysr, a.ysi, 0, s, -1,
+                                  st == 1 ? &pending : nullptr);
     if (e != hipSuccess) return e;
-    e = launch_epilogue(pv, a, w, s);
+    const bool carry = sparse && st == 0;
+    e = launch_epilogue(pv, a, w, s, !carry);
     if (e != hipSuccess) return e;
+    if (carry) pending = finish_job(pv, a, w);
   }
   return launch_rkf_commit(w.yn_r, w.yn_i, w.p_n, w.cand_r, w.cand_i, w.p_c, P->n, P->ld, w.st, s);
 }

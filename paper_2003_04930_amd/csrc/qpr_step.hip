@@ -73,18 +73,48 @@ __device__ __forceinline__ void tile_partials(double my_sum, int my_bad, double 
   }
 }
 
-__device__ __forceinline__ void reduce_partials(const double* partials, int nb, double* red,
-                                                double& tot, int& bad, double& mx) {
-  const int tid = threadIdx.x;
-  double acc = 0.0, bb = 0.0, mm = 0.0;
-  for (int i = tid; i < nb; i += ETHREADS) {
-    acc += partials[3 * i];
-    bb = fmax(bb, partials[3 * i + 1]);
-    mm = fmax(mm, partials[3 * i + 2]);
+// The fold of one stage's partials by a 256-thread workgroup in a fixed order:
+// thread t takes partials t + 256 j, accumulating j mod 4 separately (four
+// loads in flight), the four combined as (0+1)+(2+3), then a fixed shuffle
+// tree per wave and the four waves in order.  Every finisher -- the finishing
+// kernels and the sparse-product launches that carry a finishing workgroup --
+// runs it with 256 threads, so they agree bit for bit.
+constexpr int FOLD_THREADS = 256;
+__device__ __forceinline__ void fold_partials(const double* partials, int nb, double& tot,
+                                              int& bad, double& mx) {
+  __shared__ double rs[FOLD_THREADS / 64], rb[FOLD_THREADS / 64], rm[FOLD_THREADS / 64];
+  const int t = threadIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0}, bb = 0.0, mm = 0.0;
+  int i = t;
+  for (; i + 3 * FOLD_THREADS < nb; i += 4 * FOLD_THREADS) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double* q = partials + 3 * (i + k * FOLD_THREADS);
+      a[k] += q[0];
+      bb = fmax(bb, q[1]);
+      mm = fmax(mm, q[2]);
+    }
   }
-  tot = block_sum(acc, red, ETHREADS / 64);
-  mx = block_max(mm, red, ETHREADS / 64);
-  bad = __syncthreads_or(bb != 0.0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)  // at most three left after the loop above
+    if (i + k * FOLD_THREADS < nb) {
+      const double* q = partials + 3 * (i + k * FOLD_THREADS);
+      a[k] += q[0];
+      bb = fmax(bb, q[1]);
+      mm = fmax(mm, q[2]);
+    }
+  const double acc = (a[0] + a[1]) + (a[2] + a[3]);
+  const double ws = wave_sum_d(acc), wb = wave_max_d(bb), wm = wave_max_d(mm);
+  if ((t & 63) == 0) {
+    rs[t >> 6] = ws;
+    rb[t >> 6] = wb;
+    rm[t >> 6] = wm;
+  }
+  __syncthreads();
+  tot = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+  bad = fmax(fmax(rb[0], rb[1]), fmax(rb[2], rb[3])) != 0.0;
+  mx = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
+  __syncthreads();
 }
 
 // Tile pairs of the upper triangle: k -> (I, J), I <= J, column by column.
@@ -437,32 +467,30 @@ __device__ void finish_control(DevState* st, int check, int fstage, double tot, 
   }
 }
 
-__global__ void __launch_bounds__(ETHREADS)
-    k_finish(const double* __restrict__ partials, int nb, DevState* __restrict__ st, int check,
-             int fstage, int gate) {
-  if (st->stop || (gate && st->hold)) return;
-  __shared__ double red[ETHREADS / 64];
+// The finishing step of a reducing stage: fold its partials and update the
+// control block.  Called by all FOLD_THREADS threads of the workgroup.
+// Inlined: an out-of-line call gives the calling kernel a stack, whose set-up
+// every wave pays (the row-major product went from 12 to 22 us at N = 922).
+__device__ __forceinline__ void run_finish(const FinishJob& f) {
+  DevState* st = f.st;
+  if (st->stop || (f.gate && st->hold)) return;  // uniform: only this step writes them
   double tot, mx;
   int bad;
-  reduce_partials(partials, nb, red, tot, bad, mx);
-  if (threadIdx.x == 0) finish_control(st, check, fstage, tot, bad, mx);
+  fold_partials(f.partials, f.nb, tot, bad, mx);
+  if (threadIdx.x == 0) finish_control(st, f.check, f.fstage, tot, bad, mx);
 }
 
+__global__ void __launch_bounds__(FOLD_THREADS) k_finish(FinishJob f) { run_finish(f); }
+
 // One workgroup per running system (grid-stride over the system list).
-__global__ void __launch_bounds__(ETHREADS)
+__global__ void __launch_bounds__(FOLD_THREADS)
     k_finish_batch(const BatchEpi* __restrict__ args, const int* __restrict__ sys_list,
                    const int* __restrict__ nsys) {
-  __shared__ double red[ETHREADS / 64];
   const int ns = *nsys;
   for (int it = blockIdx.x; it < ns; it += gridDim.x) {
     const BatchEpi& e = args[sys_list[it]];
-    DevState* st = e.st;
-    if (st->stop || (e.a.gate && st->hold)) continue;
-    double tot, mx;
-    int bad;
-    reduce_partials(e.partials, tri_tiles(e.pv.ld / TE), red, tot, bad, mx);
-    if (threadIdx.x == 0) finish_control(st, e.a.check, fehlberg_stage(e.a.mode), tot, bad, mx);
-    __syncthreads();
+    run_finish(FinishJob{e.partials, tri_tiles(e.pv.ld / TE), e.st, e.a.check,
+                         fehlberg_stage(e.a.mode), e.a.gate});
   }
 }
 
@@ -517,6 +545,8 @@ __global__ void __launch_bounds__(ETHREADS)
 // Rows a >= n are left untouched (the epilogue never reads them).
 constexpr int SP_COLS = 128;
 constexpr int SP_WAVES = 4;
+static_assert(2 * SP_COLS == FOLD_THREADS && 64 * SP_WAVES == FOLD_THREADS,
+              "a sparse-product workgroup can run the finishing step");
 
 // Sum over the neighbour rows j of a of Y_s[j * ld] for S streams (pointers
 // already offset to the lane's column); the row range [e0, e1) is uniform.
@@ -641,11 +671,19 @@ __device__ __forceinline__ int spmm_xcd_remap(int bid, int nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// The row-major and FP32 product launches may carry the finishing step of
+// the previous stage as one extra workgroup, the first one dispatched
+// (f.nb > 0), so that it overlaps the product: the product itself does not
+// depend on the control block, and the next epilogue checks the flags that
+// step sets.  The chunk-major FP64 kernels do not (FinishJob unused): at
+// 124-128 VGPRs the call took the registers that keep a group's gathers in
+// flight, and where they are the default (N >= 1536) a separate finishing
+// launch costs < 0.5 % of a stage.
 template <int W, int RPW>
 __global__ void __launch_bounds__(64 * SP_WAVES)
     k_spmm_cm(ProbView pv, const double* __restrict__ yr, const double* __restrict__ yi,
               double* __restrict__ xr, double* __restrict__ xi, const DevState* __restrict__ st,
-              int gate) {
+              int gate, FinishJob) {
   if (st->stop || (gate && st->hold)) return;
   spmm_cm_group<W, RPW>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -653,11 +691,17 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
 __global__ void __launch_bounds__(2 * SP_COLS)
     k_spmm(ProbView pv, const double* __restrict__ yr, const double* __restrict__ yi,
            double* __restrict__ xr, double* __restrict__ xi, const DevState* __restrict__ st,
-           int gate) {
+           int gate, FinishJob f) {
+  const int extra = f.nb > 0;
+  if (extra && blockIdx.x == 0) {
+    run_finish(f);
+    return;
+  }
   if (st->stop || (gate && st->hold)) return;
   const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
-  const int a = __builtin_amdgcn_readfirstlane(blockIdx.x / chunks);
-  const int t = threadIdx.x, c = (blockIdx.x % chunks) * SP_COLS + (t & (SP_COLS - 1));
+  const int bid = blockIdx.x - extra;
+  const int a = __builtin_amdgcn_readfirstlane(bid / chunks);
+  const int t = threadIdx.x, c = (bid % chunks) * SP_COLS + (t & (SP_COLS - 1));
   if (c >= pv.ld) return;
   const double* const b[1] = {(t < SP_COLS ? yr : yi) + c};
   double o[1];
@@ -718,9 +762,14 @@ template <int W>
 __global__ void __launch_bounds__(64 * SP_WAVES)
     k_spmm_f32(ProbView pv, const float* __restrict__ yr, const float* __restrict__ yi,
                float* __restrict__ xr, float* __restrict__ xi, const DevState* __restrict__ st,
-               int gate) {
+               int gate, FinishJob f) {
+  const int extra = f.nb > 0;
+  if (extra && blockIdx.x == 0) {
+    run_finish(f);
+    return;
+  }
   if (st->stop || (gate && st->hold)) return;
-  spmm_f32_group<W>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x, gridDim.x));
+  spmm_f32_group<W>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x - extra, gridDim.x - extra));
 }
 
 // Persistent FP32 form over the (system, chunk * groups + group) items of the
@@ -1025,6 +1074,10 @@ ProbView view_of(const qpr_problem* P) {
                   P->h_ptr,    P->h_idx,    -1};
 }
 
+FinishJob finish_job(const ProbView& pv, const EpiArgs& a, const Ws& w) {
+  return FinishJob{w.partials, tri_tiles(pv.ld / TE), w.st, a.check, fehlberg_stage(a.mode), a.gate};
+}
+
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
                            bool finish) {
   const int grid = tri_tiles(pv.ld / TE);
@@ -1037,14 +1090,13 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else
     return hipErrorInvalidValue;
-  if (finish && reduces(a.mode))
-    k_finish<<<1, ETHREADS, 0, s>>>(w.partials, grid, w.st, a.check, fehlberg_stage(a.mode), a.gate);
+  if (finish && reduces(a.mode)) k_finish<<<1, FOLD_THREADS, 0, s>>>(finish_job(pv, a, w));
   return hipGetLastError();
 }
 
 namespace {
 typedef void (*SpmmFn)(ProbView, const double*, const double*, double*, double*, const DevState*,
-                       int);
+                       int, FinishJob);
 struct SpmmVariant {
   const char* name;
   SpmmFn fn;
@@ -1070,21 +1122,28 @@ int spmm_default_variant(const ProbView& pv) {
 }
 
 hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, double* xr,
-                       double* xi, const DevState* st, int gate, hipStream_t s, int variant) {
+                       double* xi, const DevState* st, int gate, hipStream_t s, int variant,
+                       const FinishJob* fin) {
+  FinishJob f = fin ? *fin : FinishJob{};
   if (variant < 0) variant = pv.spmm_variant >= 0 ? pv.spmm_variant : spmm_default_variant(pv);
   if (variant >= kNumSpmm) return hipErrorInvalidValue;
   // ld is a multiple of 64 only: a 128-column chunk size that does not divide
   // it falls back to 64 columns (same sums, same bits)
   if (kSpmm[variant].cols == 128 && pv.ld % 128 != 0) variant = 1;  // cm_w64_r1
   const SpmmVariant& v = kSpmm[variant];
+  if (v.cols != 0 && f.nb > 0) {  // chunk-major: finish in its own launch first
+    k_finish<<<1, FOLD_THREADS, 0, s>>>(f);
+    f = FinishJob{};
+  }
+  const int extra = f.nb > 0 ? 1 : 0;
   int grid;
   if (v.cols == 0) {
     grid = pv.n * ((pv.ld + SP_COLS - 1) / SP_COLS);
-    v.fn<<<grid, 2 * SP_COLS, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+    v.fn<<<grid + extra, 2 * SP_COLS, 0, s>>>(pv, yr, yi, xr, xi, st, gate, f);
   } else {
     const int groups = (pv.n + SP_WAVES * v.rpw - 1) / (SP_WAVES * v.rpw);
     grid = (pv.ld / v.cols) * groups;
-    v.fn<<<grid, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+    v.fn<<<grid + extra, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate, f);
   }
   return hipGetLastError();
 }
@@ -1096,12 +1155,17 @@ hipError_t launch_spmm_f32_batch(const BatchEpi* args, const int2* items, const 
 }
 
 hipError_t launch_spmm_f32(const ProbView& pv, const float* yr, const float* yi, float* xr,
-                           float* xi, const DevState* st, int gate, hipStream_t s) {
+                           float* xi, const DevState* st, int gate, hipStream_t s,
+                           const FinishJob* fin) {
+  const FinishJob f = fin ? *fin : FinishJob{};
+  const int extra = f.nb > 0 ? 1 : 0;
   const int groups = (pv.n + SP_WAVES - 1) / SP_WAVES;
   if (pv.ld % 128 == 0)
-    k_spmm_f32<128><<<(pv.ld / 128) * groups, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+    k_spmm_f32<128><<<(pv.ld / 128) * groups + extra, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi,
+                                                                           st, gate, f);
   else
-    k_spmm_f32<64><<<(pv.ld / 64) * groups, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi, st, gate);
+    k_spmm_f32<64><<<(pv.ld / 64) * groups + extra, 64 * SP_WAVES, 0, s>>>(pv, yr, yi, xr, xi,
+                                                                         st, gate, f);
   return hipGetLastError();
 }
 
@@ -1126,7 +1190,7 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
     k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else
     return hipErrorInvalidValue;
-  if (finish) k_finish_batch<<<256, ETHREADS, 0, s>>>(args, sys_list, nsys);
+  if (finish) k_finish_batch<<<256, FOLD_THREADS, 0, s>>>(args, sys_list, nsys);
   return hipGetLastError();
 }
 
