@@ -315,6 +315,123 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
   }
 }
 
+// Single-LDS-buffer form of the BF16x3 product: the next k-slab is staged in
+// registers while the current one is multiplied out of LDS, so a workgroup
+// holds one slab (A: BM x 32, B: 6 x BN x 32 bf16) instead of two, and two or
+// three workgroups share a CU (the double-buffered 128x64 tile fits only one,
+// a single wave per SIMD).  A larger BM amortises the six B slices over more
+// rows of H.  Same fragment layout and slice order as k_gemm_bf16x3, so the
+// product is bitwise the same.
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_bf16x3_sb(const uint16_t* __restrict__ H, const uint16_t* __restrict__ sl,
+                     float* __restrict__ Xr, float* __restrict__ Xi, int ld,
+                     const DevState* __restrict__ st, int gate) {
+  constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
+  constexpr int BK = 32, RS = BK + 8;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int UA = BM * (BK / 8), UB = 6 * BN * (BK / 8);  // uint4 units per slab
+  constexpr int NA = (UA + NT - 1) / NT, NB = (UB + NT - 1) / NT;
+  __shared__ uint16_t As[BM * RS];
+  __shared__ uint16_t Bs[6 * BN * RS];
+  if (st->stop || (gate && st->hold)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (logical % tiles_m) * BM, n0 = (logical / tiles_m) * BN;
+  const int wm0 = (wave % NWM) * WM, wn0 = (wave / NWM) * WN;
+  const size_t plane = (size_t)ld * ld;
+
+  f4 acc[2][FM][FN];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[p][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  uint4 ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT;
+      if (UA % NT == 0 || v < UA)
+        ra[u] = *reinterpret_cast<const uint4*>(H + (size_t)(m0 + v / 4) * ld + k0 + 8 * (v % 4));
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT;
+      if (UB % NT == 0 || v < UB) {
+        const int ps = v / (BN * 4), rem = v % (BN * 4);
+        rb[u] = *reinterpret_cast<const uint4*>(sl + ps * plane + (size_t)(n0 + rem / 4) * ld +
+                                                k0 + 8 * (rem % 4));
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT;
+      if (UA % NT == 0 || v < UA)
+        *reinterpret_cast<uint4*>(&As[(v / 4) * RS + 8 * (v % 4)]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT;
+      if (UB % NT == 0 || v < UB) {
+        const int ps = v / (BN * 4), rem = v % (BN * 4);
+        *reinterpret_cast<uint4*>(&Bs[(ps * BN + rem / 4) * RS + 8 * (rem % 4)]) = rb[u];
+      }
+    }
+  };
+
+  const int KT = ld / BK;
+  gload(0);
+  lstore();
+  __syncthreads();
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int kt = 0; kt < KT; ++kt) {
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+    bf8 a[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      a[i] = *reinterpret_cast<const bf8*>(&As[(wm0 + i * 16 + lc) * RS + 8 * lr]);
+#pragma unroll
+    for (int ps = 0; ps < 6; ++ps) {
+      const int p = ps / 3;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bf8 b =
+            *reinterpret_cast<const bf8*>(&Bs[(ps * BN + wn0 + j * 16 + lc) * RS + 8 * lr]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[p][i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (kt + 1 < KT) {
+      lstore();
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    float* X = p ? Xi : Xr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm0 + i * 16 + 4 * lr + r;
+          const int col = n0 + wn0 + j * 16 + lc;
+          X[(size_t)row * ld + col] = acc[p][i][j][r];
+        }
+  }
+}
+
 template <typename Fn>
 struct GemmCfg {
   int bm, bn;
@@ -355,6 +472,10 @@ const GemmCfg<BFFn> kBF[] = {
     {32, 32, "bf16x3_32x32_w32x32", k_gemm_bf16x3<32, 32, 32, 32>, 64},
     {64, 64, "bf16x3_64x64_w64x32", k_gemm_bf16x3<64, 64, 64, 32>, 128},
     {128, 64, "bf16x3_128x64_w64x32", k_gemm_bf16x3<128, 64, 64, 32>, 256},
+    {128, 64, "bf16x3_128x64_w64x32_sb", k_gemm_bf16x3_sb<128, 64, 64, 32>, 256},
+    {256, 64, "bf16x3_256x64_w64x32_sb", k_gemm_bf16x3_sb<256, 64, 64, 32>, 512},
+    {128, 128, "bf16x3_128x128_w64x64_sb", k_gemm_bf16x3_sb<128, 128, 64, 64>, 256},
+    {256, 128, "bf16x3_256x128_w64x64_sb", k_gemm_bf16x3_sb<256, 128, 64, 64>, 512},
 };
 constexpr int kNumF64 = sizeof(kF64) / sizeof(kF64[0]);
 constexpr int kNumF32 = sizeof(kF32) / sizeof(kF32[0]);
@@ -422,6 +543,10 @@ int gemm_default_cfg(int kind, int n) {
   const bool big = ld >= 2048 && ld % 128 == 0;
   if (kind == OP_F64) return big ? 10 : 1;
   if (kind == OP_F32) return big ? 0 : 5;
+  // BF16x3: single-LDS-buffer tiles with 256 rows of H where ld allows
+  // (4096: 256x128, 1.88 ms; 2048: 256x64, 0.23 ms)
+  if (ld % 256 == 0 && ld >= 4096) return 7;
+  if (ld % 256 == 0 && ld >= 2048) return 5;
   return big ? 3 : 0;
 }
 

@@ -98,3 +98,28 @@ def test_lowp_rk4_trajectory_close_to_fp64(Q):
         Q.rk4_step(P, 0.5, 0.01, 30, x, prec=prec, product=product)
         err = (x - x64).abs().max().item()
         assert 0 < err < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_every_dense_tile_configuration(Q, prec):
+    """Every tile configuration of the dense product runs the MFMA
+    accumulation along k in the same order (and, for BF16x3, the slices in the
+    same order), so all give bitwise the same right-hand side; it matches the
+    oracle within the precision's bound.  N = 250 pads to ld = 256, which every
+    tile shape divides."""
+    g = inputs.ba_digraph(250, 3, seed=21)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    rho = inputs.random_density(g.n, seed=22)
+    want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.4)
+    deg = int((R.H != 0).sum(axis=1).max())
+    bound = (1e-12 if prec == "fp64" else
+             8 * 2.0 ** -24 * (deg + 1) * np.max(np.abs(rho)) * 0.6 + 1e-15)
+    names = Q.product_configs(prec)
+    outs = []
+    for cfg, name in enumerate(names):
+        got = Q.to_complex(Q.rhs(P, 0.4, Q.planar(rho), prec=prec, product="dense", gemm_cfg=cfg))
+        assert np.max(np.abs(got - want)) <= bound, name
+        outs.append(got)
+    for name, got in zip(names[1:], outs[1:]):
+        assert np.array_equal(got, outs[0]), name
