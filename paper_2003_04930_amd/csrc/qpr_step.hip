@@ -772,10 +772,26 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
   spmm_f32_group<W>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x - extra, gridDim.x - extra));
 }
 
-// Persistent FP32 form over the (system, chunk * groups + group) items of the
-// 32-column chunking; operand = the system's FP32 state copy (a.lor), result
-// into its FP32 product planes (a.xfr).
-__global__ void __launch_bounds__(64 * SP_WAVES)
+// One row-major item (row a, 128-column chunk) of the sparse product for the
+// batched kernels (the systems of a batch have N <= ~1000, where the row-major
+// layout is fastest): thread t takes plane t / 128 and column c0 + t % 128.
+template <typename T, typename TX>
+__device__ __forceinline__ void spmm_row_item(const ProbView& pv, const T* __restrict__ yr,
+                                              const T* __restrict__ yi, TX* __restrict__ xr,
+                                              TX* __restrict__ xi, int item) {
+  const int chunks = (pv.ld + SP_COLS - 1) / SP_COLS;
+  const int a = __builtin_amdgcn_readfirstlane(item / chunks);
+  const int t = threadIdx.x, c = (item % chunks) * SP_COLS + (t & (SP_COLS - 1));
+  if (c >= pv.ld) return;
+  const T* const b[1] = {(t < SP_COLS ? yr : yi) + c};
+  double o[1];
+  gather_rows<1, false, T>(pv.h_idx, pv.h_ptr[a], pv.h_ptr[a + 1], pv.ld, b, o);
+  (t < SP_COLS ? xr : xi)[(size_t)a * pv.ld + c] = (TX)((double)pv.hsign * o[0]);
+}
+
+// Persistent FP32 form over (system, row * chunks + chunk) items; operand =
+// the system's FP32 state copy (a.lor), result into its FP32 product planes.
+__global__ void __launch_bounds__(2 * SP_COLS)
     k_spmm_f32_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
                      const int* __restrict__ nitems) {
   const int ni = *nitems;
@@ -783,13 +799,12 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
     const int2 item = items[it];
     const BatchEpi& e = args[item.x];
     if (e.st->stop || (e.a.gate && e.st->hold)) continue;
-    spmm_f32_group<32>(e.pv, e.a.lor, e.a.loi, (float*)e.a.xfr, (float*)e.a.xfi, item.y);
+    spmm_row_item<float, float>(e.pv, e.a.lor, e.a.loi, (float*)e.a.xfr, (float*)e.a.xfi, item.y);
   }
 }
 
-// Persistent form over (system, chunk * groups + group) items of the W = 32,
-// RPW = 1 chunk-major variant (batched systems are small: no XCD remap).
-__global__ void __launch_bounds__(64 * SP_WAVES)
+// Persistent FP64 form over (system, row * chunks + chunk) items.
+__global__ void __launch_bounds__(2 * SP_COLS)
     k_spmm_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
                  const int* __restrict__ nitems) {
   const int ni = *nitems;
@@ -797,7 +812,8 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
     const int2 item = items[it];
     const BatchEpi& e = args[item.x];
     if (e.st->stop || (e.a.gate && e.st->hold)) continue;
-    spmm_cm_group<32, 1>(e.pv, e.a.ysr, e.a.ysi, (double*)e.a.xr, (double*)e.a.xi, item.y);
+    spmm_row_item<double, double>(e.pv, e.a.ysr, e.a.ysi, (double*)e.a.xr, (double*)e.a.xi,
+                                  item.y);
   }
 }
 
@@ -1150,7 +1166,7 @@ hipError_t launch_spmm(const ProbView& pv, const double* yr, const double* yi, d
 
 hipError_t launch_spmm_f32_batch(const BatchEpi* args, const int2* items, const int* nitems,
                                  int grid, hipStream_t s) {
-  k_spmm_f32_batch<<<grid, 64 * SP_WAVES, 0, s>>>(args, items, nitems);
+  k_spmm_f32_batch<<<grid, 2 * SP_COLS, 0, s>>>(args, items, nitems);
   return hipGetLastError();
 }
 
@@ -1169,13 +1185,13 @@ hipError_t launch_spmm_f32(const ProbView& pv, const float* yr, const float* yi,
   return hipGetLastError();
 }
 
-int spmm_items_per_system(int n, int ld) { return (ld / 32) * spmm_cm_groups<1>(n); }
+int spmm_items_per_system(int n, int ld) { return n * ((ld + SP_COLS - 1) / SP_COLS); }
 
 int epilogue_items_per_system(int ld) { return tri_tiles(ld / TE); }
 
 hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int* nitems, int grid,
                              hipStream_t s) {
-  k_spmm_batch<<<grid, 64 * SP_WAVES, 0, s>>>(args, items, nitems);
+  k_spmm_batch<<<grid, 2 * SP_COLS, 0, s>>>(args, items, nitems);
   return hipGetLastError();
 }
 
