@@ -28,9 +28,9 @@ void clear_error();
                          hipGetErrorString(e_), __FILE__, __LINE__);           \
   } while (0)
 
-// Device-resident control block of one solve.  Written only by the last
-// workgroup of a reducing launch (one lane, vector stores) and read by every
-// later launch on the stream.
+// Device-resident control block of one solve.  Written by one lane of the
+// finishing step of a reducing stage (and of the final-state statistics
+// kernel), with vector stores, and read by every later launch on the stream.
 struct DevState {
   double resid2;        // ||L(y_n)||_F^2 measured by the latest stage-1 pass
   double tol2;          // tol^2
@@ -42,7 +42,7 @@ struct DevState {
   int converged;
   int nonfinite;
   int check;            // 1: stage 1 tests the tolerance
-  unsigned int ticket;  // last-workgroup counter, reset by the last workgroup
+  unsigned int ticket;  // last-workgroup counter of the final-state statistics
   int hold;             // non-zero: low-precision step launches return at once
   double judge2;        // mixed precision: latest FP64 ||L(rho_a)||_F^2
   long long folds;      // mixed precision: FP64 judge evaluations

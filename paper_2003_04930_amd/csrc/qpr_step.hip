@@ -14,9 +14,10 @@
 //
 // The same pass applies the classical RK4 stage update of Supplementary
 // Note 2 (k_s = L(Y_s); Y_{s+1} = y_n + c_s dt k_s; acc accumulates k with
-// weights 1,2,2,1; y_{n+1} = y_n + dt/6 (acc + k_4)), reduces ||k_1||_F^2 and a
-// non-finite flag with a deterministic two-level reduction, and (stage 1)
-// decides convergence on the device.
+// weights 1,2,2,1; y_{n+1} = y_n + dt/6 (acc + k_4)) and, on reducing stages,
+// leaves per-tile partials of ||k||_F^2 and a non-finite flag; a finishing
+// step folds them in a fixed order and decides convergence (or the adaptive
+// step) on the device.
 #include <cmath>
 #include <cstdio>
 
