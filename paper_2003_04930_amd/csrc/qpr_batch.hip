@@ -408,8 +408,9 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       sl.push_back(k);
     }
   };
-  int* h_counts = nullptr;
-  QPR_HIP(hipHostMalloc((void**)&h_counts, 5 * sizeof(int), hipHostMallocDefault));
+  HostPinned counts_buf;
+  QPR_HIP(hipHostMalloc(&counts_buf.h, 5 * sizeof(int), hipHostMallocDefault));
+  int* h_counts = (int*)counts_buf.h;
   auto upload_lists = [&]() -> hipError_t {
     hipError_t e = hipMemcpyAsync(d_items_g, ig.data(), ig.size() * sizeof(int2), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_items_e, ie.data(), ie.size() * sizeof(int2), hipMemcpyHostToDevice, s);
@@ -435,9 +436,10 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     if (o.gemm_cfg >= 0 && o.gemm_cfg < ncand) {
       gcfg = cands[o.gemm_cfg];
     } else {
-      hipEvent_t e0, e1;
-      QPR_HIP(hipEventCreate(&e0));
-      QPR_HIP(hipEventCreate(&e1));
+      HipEvent ev0, ev1;
+      QPR_HIP(hipEventCreate(&ev0.h));
+      QPR_HIP(hipEventCreate(&ev1.h));
+      hipEvent_t e0 = ev0.h, e1 = ev1.h;
       float best = 1e30f;
       for (int c = 0; c < ncand; ++c) {
         // a dense FP64 judge shares the item list, so it needs 64-wide tiles
@@ -458,8 +460,6 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
           gcfg = cands[c];
         }
       }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
     }
     gtile = batch_gemm_tile(gcfg);
   }
@@ -515,18 +515,19 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     }
     return mixed ? enqueue_fold_judge(qs) : hipSuccess;
   };
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cs = nullptr;
+  HipStream cap_stream;
+  HipGraph graph_h;
+  HipGraphExec exec_h;
   if (o.use_graph) {
-    QPR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    QPR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_chunk(cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    QPR_HIP(hipStreamCreateWithFlags(&cap_stream.h, hipStreamNonBlocking));
+    QPR_HIP(hipStreamBeginCapture(cap_stream.h, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_chunk(cap_stream.h);
+    hipError_t e2 = hipStreamEndCapture(cap_stream.h, &graph_h.h);
     QPR_HIP(e);
     QPR_HIP(e2);
-    QPR_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    QPR_HIP(hipGraphInstantiate(&exec_h.h, graph_h.h, nullptr, nullptr, 0));
   }
+  hipGraphExec_t exec = exec_h.h;
   std::vector<DevState> hs(nsys);
   qpr_status rc = QPR_OK;
   for (;;) {
@@ -558,10 +559,6 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       }
     }
   }
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
-  if (cs) hipStreamDestroy(cs);
-  hipHostFree(h_counts);
   if (rc != QPR_OK) return rc;
 
   // results: state, ranking and diagnostics per system

@@ -28,6 +28,44 @@ void clear_error();
                          hipGetErrorString(e_), __FILE__, __LINE__);           \
   } while (0)
 
+// Owners of HIP runtime objects, released on every return path (locals are
+// destroyed in reverse order: declare a graph before its executable).
+struct HipEvent {
+  hipEvent_t h = nullptr;
+  HipEvent() = default;
+  HipEvent(const HipEvent&) = delete;
+  HipEvent& operator=(const HipEvent&) = delete;
+  ~HipEvent() { if (h) (void)hipEventDestroy(h); }
+};
+struct HipStream {
+  hipStream_t h = nullptr;
+  HipStream() = default;
+  HipStream(const HipStream&) = delete;
+  HipStream& operator=(const HipStream&) = delete;
+  ~HipStream() { if (h) (void)hipStreamDestroy(h); }
+};
+struct HipGraph {
+  hipGraph_t h = nullptr;
+  HipGraph() = default;
+  HipGraph(const HipGraph&) = delete;
+  HipGraph& operator=(const HipGraph&) = delete;
+  ~HipGraph() { if (h) (void)hipGraphDestroy(h); }
+};
+struct HipGraphExec {
+  hipGraphExec_t h = nullptr;
+  HipGraphExec() = default;
+  HipGraphExec(const HipGraphExec&) = delete;
+  HipGraphExec& operator=(const HipGraphExec&) = delete;
+  ~HipGraphExec() { if (h) (void)hipGraphExecDestroy(h); }
+};
+struct HostPinned {
+  void* h = nullptr;
+  HostPinned() = default;
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  ~HostPinned() { if (h) (void)hipHostFree(h); }
+};
+
 // Device-resident control block of one solve.  Written by one lane of the
 // finishing step of a reducing stage (and of the final-state statistics
 // kernel), with vector stores, and read by every later launch on the stream.

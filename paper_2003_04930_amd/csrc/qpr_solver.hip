@@ -746,8 +746,9 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   const bool sparse = cfg <= -2 && xk != OP_BF16X3;
   const int spv = cfg <= -3 ? -3 - cfg : -1;
   if (sparse && spv >= spmm_num_variants()) return fail(QPR_E_ARG, "no such sparse-product variant");
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  for (auto& e : ev) QPR_HIP(hipEventCreate(&e));
+  HipEvent evh[3];
+  for (auto& e : evh) QPR_HIP(hipEventCreate(&e.h));
+  hipEvent_t ev[3] = {evh[0].h, evh[1].h, evh[2].h};
   auto product = [&]() {
     return launch_product(P, w, pv, xk, cfg, sparse, w.y1_r, w.y1_i, 0, s, spv);
   };
@@ -766,7 +767,6 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   float t0 = 0.f, t1 = 0.f;
   QPR_HIP(hipEventElapsedTime(&t0, ev[0], ev[1]));
   QPR_HIP(hipEventElapsedTime(&t1, ev[1], ev[2]));
-  for (auto& e : ev) hipEventDestroy(e);
   ms_out[0] = (double)t0 / reps;
   ms_out[1] = (double)t1 / (4.0 * reps);
   return QPR_OK;
@@ -794,9 +794,10 @@ extern "C" qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t r
   QPR_HIP(launch_fill(w.y1_r, 2 * plane * 8, s));
   if (xk == OP_F32) QPR_HIP(launch_fill(w.lo_r, 2 * plane * 4, s));
   if (xk == OP_BF16X3) QPR_HIP(launch_fill(w.sl, 6 * plane * 2, s));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  QPR_HIP(hipEventCreate(&e0));
-  QPR_HIP(hipEventCreate(&e1));
+  HipEvent ev0, ev1;
+  QPR_HIP(hipEventCreate(&ev0.h));
+  QPR_HIP(hipEventCreate(&ev1.h));
+  hipEvent_t e0 = ev0.h, e1 = ev1.h;
   int best = -1;
   double best_us = 1e300;
   for (int c = 0; c < ncfg; ++c) {
@@ -818,8 +819,6 @@ extern "C" qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t r
     }
     if (us_out) us_out[c] = us;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (best < 0) return fail(QPR_E_HIP, "no product configuration ran");
   gemm_set_tuned(xk, P->ld, best);
   if (best_cfg) *best_cfg = best;
