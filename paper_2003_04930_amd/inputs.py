@@ -127,10 +127,12 @@ def random_hermitian(n: int, seed: int = 0) -> np.ndarray:
     return 0.5 * (x + x.conj().T)
 
 
-def random_density(n: int, seed: int = 0) -> np.ndarray:
-    """Random full-rank density matrix X X^dagger / tr (complex128, trace 1)."""
+def random_density(n: int, seed: int = 0, rank: int | None = None) -> np.ndarray:
+    """Random density matrix X X^dagger / tr (complex128, trace 1); X is n x n
+    (full rank) or n x rank."""
     rng = np.random.default_rng(seed)
-    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    k = n if rank is None else rank
+    x = rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))
     r = x @ x.conj().T
     r = 0.5 * (r + r.conj().T)
     return r / np.trace(r).real

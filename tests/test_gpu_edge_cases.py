@@ -99,3 +99,29 @@ def test_doubly_stochastic_fixed_point(Q, product):
         out = Q.steady_state(P, omega, 0.01, 1e-12, 1000, product=product)
         assert out.stats["converged"] == 1 and out.stats["steps"] == 0
         assert np.max(np.abs(Q.to_complex(out.rho) - np.eye(24) / 24)) < 1e-15
+
+
+@pytest.fixture(scope="module")
+def n8192(Q):
+    """BA N = 8192 (m = 4) with a rank-16 random density (any Hermitian
+    trace-one state serves) and the oracle's right-hand side and RK4 step."""
+    n = 8192
+    g = inputs.ba_digraph(n, 4, seed=0)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    rho = inputs.random_density(n, seed=3, rank=16)
+    f = lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, 0.7)
+    return Q.Problem.from_graph(g), rho, f(rho), O.rk4_ref(rho, f, 0.01, 1)
+
+
+@pytest.mark.parametrize("product", ["sparse", "dense"])
+def test_rhs_and_stages_at_n8192(Q, n8192, product):
+    """The largest size tested: the right-hand side and one RK4 step (all four
+    stage kernels) against the oracle over every element."""
+    P, rho, want_rhs, want_step = n8192
+    got = Q.to_complex(Q.rhs(P, 0.7, Q.planar(rho), product=product))
+    assert np.max(np.abs(got - want_rhs)) < 1e-12 * max(1.0, np.max(np.abs(want_rhs)))
+    assert np.array_equal(got, got.conj().T)
+    del got
+    x = Q.planar(rho)
+    Q.rk4_step(P, 0.7, 0.01, 1, x, product=product)
+    assert np.max(np.abs(Q.to_complex(x) - want_step)) < 1e-12
