@@ -378,6 +378,11 @@ qpr_status qpr_load_tuning(const char* cache_path);
 int32_t qpr_product_configs(int32_t prec);
 const char* qpr_product_config_name(int32_t prec, int32_t cfg);
 
+/* Number of sparse-product kernel variants (qpr_opts.sparse_variant - 1,
+ * qpr_time_kernels cfg -3 - v), and their names; NULL for an invalid v. */
+int32_t qpr_sparse_variants(void);
+const char* qpr_sparse_variant_name(int32_t v);
+
 /*
  * Hub classes of the results section: counts[0] = #{i : p_i > c/N} (main
  * hubs), counts[1] = #{i : 1/N < p_i <= c/N} (secondary hubs); the paper

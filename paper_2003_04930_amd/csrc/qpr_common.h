@@ -239,7 +239,6 @@ struct BatchEpi {
   double* partials;
 };
 int batch_gemm_cfgs(int kind, int* out, int max);
-const char* batch_gemm_name(int cfg);
 int batch_gemm_tile(int cfg);
 hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,
                              const int* nitems, int grid, hipStream_t s);

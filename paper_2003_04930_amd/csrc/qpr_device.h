@@ -94,10 +94,9 @@ __device__ __forceinline__ double gain_finish(const GainView& g, int a, const do
   return g.alpha * (s + dang) + (1.0 - g.alpha) * tel;
 }
 
-// (G p)_a for G = alpha S + (1 - alpha) T with dangling columns set to T.
+// (G p)_a for G = alpha S + (1 - alpha) T with dangling columns set to T,
+// summing the in-links of a in one thread.
 //   P = sum_j p_j,  D = sum over dangling j of p_j.
-// Paper teleport F (Eq. (S2)): sum_j F_aj p_j = (P - p_a) / (N - 1).
-// Uniform teleport: sum_j p_j / N.
 __device__ __forceinline__ double gain_row(const GainView& g, int a, const double* p,
                                            double P, double D) {
   double s = 0.0;
@@ -106,18 +105,7 @@ __device__ __forceinline__ double gain_row(const GainView& g, int a, const doubl
     const int j = g.in_idx[e];
     s += p[j] * g.inv_outdeg[j];
   }
-  double tel, dang;
-  if (g.teleport == QPR_TELEPORT_PAPER_F) {
-    const double inv = 1.0 / (double)(g.n - 1);
-    const double pa = p[a];
-    tel = (P - pa) * inv;
-    dang = (D - (g.dangling[a] ? pa : 0.0)) * inv;
-  } else {
-    const double inv = 1.0 / (double)g.n;
-    tel = P * inv;
-    dang = D * inv;
-  }
-  return g.alpha * (s + dang) + (1.0 - g.alpha) * tel;
+  return gain_finish(g, a, p, P, D, s);
 }
 
 }  // namespace qpr

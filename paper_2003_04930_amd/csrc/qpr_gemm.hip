@@ -604,7 +604,6 @@ int batch_gemm_cfgs(int kind, int* out, int max) {
     if (kBatch[i].kind == kind && c < max) out[c++] = i;
   return c;
 }
-const char* batch_gemm_name(int cfg) { return cfg >= 0 && cfg < kNumBatch ? kBatch[cfg].name : "?"; }
 int batch_gemm_tile(int cfg) { return cfg >= 0 && cfg < kNumBatch ? kBatch[cfg].bm : 64; }
 
 hipError_t launch_gemm_batch(int cfg, const BatchGemm* args, const int2* items,

@@ -774,6 +774,10 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
 
 extern "C" int32_t qpr_product_configs(int32_t prec) { return gemm_num_cfgs(op_kind(prec)); }
 
+extern "C" int32_t qpr_sparse_variants(void) { return spmm_num_variants(); }
+
+extern "C" const char* qpr_sparse_variant_name(int32_t v) { return spmm_variant_name(v); }
+
 extern "C" const char* qpr_product_config_name(int32_t prec, int32_t cfg) {
   return gemm_cfg_name(op_kind(prec), cfg);
 }

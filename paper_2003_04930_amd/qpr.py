@@ -37,6 +37,7 @@ EXPORTS = (
     "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
     "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam", "qpr_autotune",
     "qpr_load_tuning", "qpr_batch_workspace_bytes", "qpr_batch_solve", "qpr_hub_counts",
+    "qpr_sparse_variants", "qpr_sparse_variant_name",
 )
 
 
@@ -125,6 +126,8 @@ def lib():
         "qpr_batch_solve": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                   C.POINTER(qpr_opts), C.POINTER(i32), vp, sz, vp]),
         "qpr_product_config_name": (C.c_char_p, [i32, i32]),
+        "qpr_sparse_variants": (i32, []),
+        "qpr_sparse_variant_name": (C.c_char_p, [i32]),
         "qpr_mpnn_param_count": (i32, []),
         "qpr_mpnn_workspace_bytes": (sz, [i32, i32]),
         "qpr_mpnn_features": (i32, [P, dbl, vp, vp, vp, vp]),
@@ -280,8 +283,18 @@ def _planar_arg(rho, n):
 
 
 # --------------------------------------------------------------- entry points
-# sparse-product kernel variants (index v = option value v + 1; -1 = default)
-SPARSE_VARIANTS = ("cm_w32_r1", "cm_w64_r1", "cm_w128_r1", "cm_w64_r2", "row128")
+
+
+def sparse_variants():
+    """Names of the sparse-product kernel variants (index v: sparse_variant=v)."""
+    L = lib()
+    return [L.qpr_sparse_variant_name(v).decode() for v in range(L.qpr_sparse_variants())]
+
+
+def __getattr__(name):
+    if name == "SPARSE_VARIANTS":
+        return tuple(sparse_variants())
+    raise AttributeError(name)
 
 
 def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto",
