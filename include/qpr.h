@@ -10,10 +10,12 @@
  *   D_G(rho) = sum_ij ( L_ij rho L_ij^dag - 1/2 {L_ij^dag L_ij, rho} ),
  *   L_ij     = sqrt(G_ij) |i><j|,
  *
- * with the classical four-stage Runge-Kutta method (Supplementary Note 2)
- * until ||L(rho)||_F < tol.  The N^2 x N^2 Liouvillian of Eq. (2) is never
- * formed: the commutator is a real matrix product X = H_off [Re rho | Im rho]
- * on the matrix cores and [H, rho] = X - X^dag + [diag(h), rho]; the jump sum
+ * with the classical four-stage Runge-Kutta method or the adaptive Fehlberg
+ * 4(5) method (Supplementary Note 2) until ||L(rho)||_F < tol.  The
+ * N^2 x N^2 Liouvillian of Eq. (2) is never formed: the commutator is one
+ * real product X = H_off [Re rho | Im rho] (dense on the matrix cores, or
+ * gathers through the sparsity pattern of H_off) and
+ * [H, rho] = X - X^dag + [diag(h), rho]; the jump sum
  * collapses to diag(G p) - 1/2 (d_a + d_b) rho_ab with p = diag(rho) and
  * d_j = sum_i G_ij.
  *
@@ -255,10 +257,12 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  * every stage kernel covers all running systems through a device-side
  * (system, tile) work list; chunks of `opts->chunk` steps are replayed as one
  * captured HIP graph, and between replays the lists are shrunk to the systems
- * still running.  prec QPR_FP64 (product per opts->product) or QPR_FP32 (FP32
- * MFMA product with the FP64 fold-and-judge defect correction of
- * qpr_steady_state, judged every chunk).  The dense-product tile configuration
- * is tuned on this batch's own work list unless opts->gemm_cfg >= 0.
+ * still running.  prec QPR_FP64 or QPR_FP32 (the FP32 product -- gathers of
+ * the FP32 copy of delta, or FP32 MFMA tiles -- with the FP64 fold-and-judge
+ * defect correction of qpr_steady_state, judged every chunk); the product
+ * follows opts->product, decided on probs[0]'s density for the whole batch.
+ * The dense-product tile configuration is tuned on this batch's own work list
+ * unless opts->gemm_cfg >= 0.
  *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are
  *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
  *           may be NULL or hold device int32[n_k] / NULL entries
