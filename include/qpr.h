@@ -160,9 +160,14 @@ typedef enum {
  * serves QPR_FP64 (FP64 operand) and QPR_FP32 (gathers of the FP32 copy of
  * the state, sums in FP64, X rounded to FP32); QPR_BF16X3 is always dense. */
 typedef enum {
-  QPR_PRODUCT_AUTO = 0,   /* sparse when H_off is below 5 % dense, else dense */
+  QPR_PRODUCT_AUTO = 0,   /* sparse when H_off is below 5 % dense, else dense; the sparse
+                             choice is FUSED from a padded size of 4096 on (FP64 stages) */
   QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
-  QPR_PRODUCT_SPARSE = 2  /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
+  QPR_PRODUCT_SPARSE = 2, /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
+  QPR_PRODUCT_FUSED = 3   /* the same gathers inside the epilogue: each tile pair gathers the two
+                             32 x 32 blocks of X it needs into LDS, so X never goes to HBM and a
+                             stage is one launch.  FP64 single-system solves only; the FP32
+                             product and qpr_batch_solve take the sparse product instead */
 } qpr_product;
 
 /* ------------------------------------------------------------------ build */
@@ -352,7 +357,8 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * both planes per wave, R rows per wave), 4 row128 (one workgroup per row and
  * 128-column chunk).  The default is row128 below N = 1536 and cm_w128_r1 above where
  * the padded size is a multiple of 128.  All variants give bitwise the same
- * product.
+ * product.  With QPR_FP64, v = qpr_sparse_variants() times the fused
+ * epilogue of QPR_PRODUCT_FUSED (no product launch: ms_out[0] = 0).
  *   rho     device, 2*n*n planar FP64 operand (unchanged)
  *   ms_out  HOST double[2]: mean milliseconds per product launch and per
  *           epilogue launch (the mean over the four stages)

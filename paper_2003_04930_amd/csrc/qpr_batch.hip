@@ -240,7 +240,8 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   // mode) below 5 % density unless opts->product says otherwise
   auto sparse_for = [&](const qpr_problem* P) {
     if (o.product == QPR_PRODUCT_DENSE) return false;
-    if (o.product == QPR_PRODUCT_SPARSE) return true;
+    // the batch has no fused epilogue: the fused mode takes the sparse product
+    if (o.product == QPR_PRODUCT_SPARSE || o.product == QPR_PRODUCT_FUSED) return true;
     return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
   };
   const bool step_sparse = sparse_for(probs[0]);
@@ -272,7 +273,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
         e.pv = pv;
         e.st = w.st;
         e.partials = w.partials;
-        e.a = rkf_stage_args(w, q, omegas[k], step_sparse);
+        e.a = rkf_stage_args(w, q, omegas[k], step_sparse ? XS_SPARSE64 : XS_DENSE64);
         g = BatchGemm{};
         g.H = P->h_off;
         g.yr = e.a.ysr;

@@ -168,7 +168,8 @@ enum OpKind { OP_F64 = 0, OP_F32 = 1, OP_BF16X3 = 2 };
 enum XSource {
   XS_DENSE64 = 0,   // FP64 X written by the dense product
   XS_DENSE32 = 1,   // FP32 X written by a low-precision dense product
-  XS_SPARSE64 = 2   // FP64 X written by the sparse product (k_spmm)
+  XS_SPARSE64 = 2,  // FP64 X written by the sparse product (k_spmm)
+  XS_FUSED64 = 3    // FP64 X gathered inside the epilogue tile (no product launch)
 };
 
 struct EpiArgs {
@@ -250,7 +251,7 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
 // Fehlberg 4(5): epilogue arguments of stage st (0..5) on a workspace, and the
 // largest step whose fourth-order update is stable for the spectrum bound of
 // the Liouvillian at omega (rho_h = spectral radius of H).
-EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse);
+EpiArgs rkf_stage_args(const Ws& w, int st, double omega, int xs);
 double rkf_step_cap(double omega, double rho_h);
 
 // variant: index into the sparse-product variants (-1 = pv.spmm_variant);

@@ -44,10 +44,26 @@ void clear_error() { g_err[0] = 0; }
 // Sparse gathers for the FP64 product when H_off is sparse enough (or forced).
 // The sparse product serves the FP64 and the FP32-operand products (there is
 // no three-slice bf16 form: its point is the MFMA throughput of dense tiles).
+// The fused mode asks for the same gathers, so it implies the sparse product
+// wherever the fused epilogue does not apply (the FP32 product).
 static bool use_sparse(const qpr_problem* P, int product, int xk) {
   if (xk == OP_BF16X3 || product == QPR_PRODUCT_DENSE) return false;
-  if (product == QPR_PRODUCT_SPARSE) return true;
+  if (product == QPR_PRODUCT_SPARSE || product == QPR_PRODUCT_FUSED) return true;
   return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
+}
+
+// Where the epilogue takes X from: the FP32 X of a low-precision product, the
+// FP64 X a separate product launch wrote (sparse or dense), or the epilogue's
+// own gathers (fused: no product launch).
+// AUTO takes the fused epilogue from a padded size of 4096 on: there a stage
+// is 13 % faster than product + epilogue; at 922 and 2048 the two kernels win
+// (the fused tile pairs run their gathers and the epilogue back to back, with
+// too few workgroups per CU to hide either).
+static int x_source(const qpr_problem* P, int product, int xk) {
+  if (xk != OP_F64) return XS_DENSE32;
+  if (product == QPR_PRODUCT_FUSED) return XS_FUSED64;
+  if (!use_sparse(P, product, xk)) return XS_DENSE64;
+  return product == QPR_PRODUCT_AUTO && P->ld >= 4096 ? XS_FUSED64 : XS_SPARSE64;
 }
 
 // The problem view with the sparse-product variant the options ask for.
@@ -212,7 +228,7 @@ static qpr_status check_dt(const qpr_problem* P, double omega, double dt) {
 // anchor residual) is added to every stage's right-hand side.
 // Epilogue arguments of classical RK4 stage k (0..3) on the workspace: the
 // stage inputs rotate y_n -> Y_1 -> Y_2 -> Y_1 and the last stage writes y_n.
-static EpiArgs rk4_stage_args(const Ws& w, int k, double omega, double dt, int xk, bool sparse,
+static EpiArgs rk4_stage_args(const Ws& w, int k, double omega, double dt, int xk, int xs,
                               int check, int gate, bool with_ra) {
   struct Stage {
     double *inr, *ini, *pin, *outr, *outi, *pout;
@@ -248,7 +264,7 @@ static EpiArgs rk4_stage_args(const Ws& w, int k, double omega, double dt, int x
   a.omega = omega;
   a.cdt = sg.cdt;
   a.mode = EPI_S1 + k;
-  a.xkind = xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
+  a.xkind = xs;
   a.check = k == 0 ? check : CHK_NONE;
   a.gate = gate;
   return a;
@@ -259,14 +275,19 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
                                hipStream_t s) {
   const int gate = check == CHK_DELTA ? 1 : 0;
   const bool sparse = use_sparse(P, product, xk);
+  const int xs = x_source(P, product, xk);
+  const bool fused = xs == XS_FUSED64;
   // with the sparse product the stage-2 launch carries stage 1's finishing step
   FinishJob pending{};
   for (int k = 0; k < 4; ++k) {
-    const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, sparse, check, gate, with_ra);
-    hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, a.ysr, a.ysi, gate, s, -1,
-                                  k == 1 ? &pending : nullptr);
-    if (e != hipSuccess) return e;
-    const bool carry = sparse && k == 0;
+    const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, xs, check, gate, with_ra);
+    hipError_t e = hipSuccess;
+    if (!fused) {
+      e = launch_product(P, w, pv, xk, cfg, sparse, a.ysr, a.ysi, gate, s, -1,
+                         k == 1 ? &pending : nullptr);
+      if (e != hipSuccess) return e;
+    }
+    const bool carry = sparse && !fused && k == 0;
     e = launch_epilogue(pv, a, w, s, !carry);
     if (e != hipSuccess) return e;
     if (carry) pending = finish_job(pv, a, w);
@@ -279,11 +300,12 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
                               double* inr, double* ini, double* pin, double* outr, double* outi,
                               int xk, int cfg, int product, int check, hipStream_t s) {
   const bool sparse = use_sparse(P, product, xk);
+  const int xs = x_source(P, product, xk);
   if (xk != OP_F64) {
     hipError_t e = launch_to_lowp(xk, inr, ini, P->n, P->ld, w, s);
     if (e != hipSuccess) return e;
   }
-  {
+  if (xs != XS_FUSED64) {
     hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, inr, ini, 0, s);
     if (e != hipSuccess) return e;
   }
@@ -299,7 +321,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
   a.outi = outi;
   a.omega = omega;
   a.mode = EPI_RHS;
-  a.xkind = xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
+  a.xkind = xs;
   a.check = check;
   return launch_epilogue(pv, a, w, s);
 }
@@ -354,7 +376,7 @@ double rkf_step_cap(double omega, double rho_h) {
 // inputs y_n -> Y_1 -> Y_2 -> Y_1 -> Y_2 -> Y_1 (stage s + 1 reads what stage s
 // wrote), K_s kept for the later stages, and the sixth stage writing the
 // fourth-order candidate and the error estimate.
-EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse) {
+EpiArgs rkf_stage_args(const Ws& w, int st, double omega, int xs) {
   double* in_r[6] = {w.yn_r, w.y1_r, w.y2_r, w.y1_r, w.y2_r, w.y1_r};
   double* in_i[6] = {w.yn_i, w.y1_i, w.y2_i, w.y1_i, w.y2_i, w.y1_i};
   double* in_p[6] = {w.p_n, w.p_1, w.p_2, w.p_1, w.p_2, w.p_1};
@@ -368,7 +390,7 @@ EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse) {
   a.yni = w.yn_i;
   a.omega = omega;
   a.mode = EPI_F1 + st;
-  a.xkind = sparse ? XS_SPARSE64 : XS_DENSE64;
+  a.xkind = xs;
   a.check = st == 0 ? CHK_RKF : CHK_NONE;
   for (int j = 0; j < 5; ++j) {
     a.kr[j] = w.k_r[j];
@@ -398,13 +420,18 @@ EpiArgs rkf_stage_args(const Ws& w, int st, double omega, bool sparse) {
 static hipError_t enqueue_rkf_attempt(const qpr_problem* P, const Ws& w, const ProbView& pv,
                                       double omega, int cfg, int product, hipStream_t s) {
   const bool sparse = use_sparse(P, product, OP_F64);
+  const int xs = x_source(P, product, OP_F64);
+  const bool fused = xs == XS_FUSED64;
   FinishJob pending{};  // stage 1's finishing step rides on the stage-2 sparse launch
   for (int st = 0; st < 6; ++st) {
-    const EpiArgs a = rkf_stage_args(w, st, omega, sparse);
-    hipError_t e = launch_product(P, w, pv, OP_F64, cfg, sparse, a.ysr, a.ysi, 0, s, -1,
-                                  st == 1 ? &pending : nullptr);
-    if (e != hipSuccess) return e;
-    const bool carry = sparse && st == 0;
+    const EpiArgs a = rkf_stage_args(w, st, omega, xs);
+    hipError_t e = hipSuccess;
+    if (!fused) {
+      e = launch_product(P, w, pv, OP_F64, cfg, sparse, a.ysr, a.ysi, 0, s, -1,
+                         st == 1 ? &pending : nullptr);
+      if (e != hipSuccess) return e;
+    }
+    const bool carry = sparse && !fused && st == 0;
     e = launch_epilogue(pv, a, w, s, !carry);
     if (e != hipSuccess) return e;
     if (carry) pending = finish_job(pv, a, w);
@@ -742,15 +769,19 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
   QPR_HIP(launch_fill(w.acc_r, 2 * (size_t)P->ld * P->ld * 8, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
-  // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v
+  // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v;
+  // v = the number of variants: the fused epilogue (no product launch)
   const bool sparse = cfg <= -2 && xk != OP_BF16X3;
   const int spv = cfg <= -3 ? -3 - cfg : -1;
-  if (sparse && spv >= spmm_num_variants()) return fail(QPR_E_ARG, "no such sparse-product variant");
+  const bool fused = sparse && xk == OP_F64 && spv == spmm_num_variants();
+  if (sparse && spv > spmm_num_variants() - (fused ? 0 : 1))
+    return fail(QPR_E_ARG, "no such sparse-product variant");
+  const int xs = fused ? XS_FUSED64 : xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
   HipEvent evh[3];
   for (auto& e : evh) QPR_HIP(hipEventCreate(&e.h));
   hipEvent_t ev[3] = {evh[0].h, evh[1].h, evh[2].h};
   auto product = [&]() {
-    return launch_product(P, w, pv, xk, cfg, sparse, w.y1_r, w.y1_i, 0, s, spv);
+    return fused ? hipSuccess : launch_product(P, w, pv, xk, cfg, sparse, w.y1_r, w.y1_i, 0, s, spv);
   };
   for (int r = 0; r < 3; ++r) QPR_HIP(product());
   QPR_HIP(hipEventRecord(ev[0], s));
@@ -760,7 +791,7 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   // computes its reductions, the finishing kernel that folds them is not timed
   for (int r = 0; r < reps; ++r)
     for (int k = 0; k < 4; ++k)
-      QPR_HIP(launch_epilogue(pv, rk4_stage_args(w, k, omega, 0.01, xk, sparse, CHK_PLAIN, 0, false),
+      QPR_HIP(launch_epilogue(pv, rk4_stage_args(w, k, omega, 0.01, xk, xs, CHK_PLAIN, 0, false),
                               w, s, false));
   QPR_HIP(hipEventRecord(ev[2], s));
   QPR_HIP(hipEventSynchronize(ev[2]));

@@ -128,6 +128,80 @@ __device__ __forceinline__ void tri_decode(int k, int& I, int& J) {
 }
 __host__ __device__ constexpr int tri_tiles(int t) { return t * (t + 1) / 2; }
 
+// The fused sparse product: the two 32 x 32 blocks of X = H_off Y that tile
+// pair (I, J) needs, gathered through the CSR of H_off straight into LDS.
+// Task t < 32 is row b0 + t of X over columns a0.. (the transposed block, into
+// Tr/Ti); task 32 + t (off-diagonal pairs) row a0 + t over columns b0.. (into
+// Xr/Xi).  Wave w owns tasks w, w + 8, ..., with the 64 lanes on (plane,
+// column).  The first eight neighbour indices of all its tasks come in one
+// vector load (lane 8 j + k: entry k of task j) and are broadcast from there,
+// so only the row loads are on the critical path; rows with more than eight
+// neighbours finish with groups of eight read through the index array.  Each
+// row is summed in CSR order.
+constexpr int FUSE_TASKS_IN_FLIGHT = 2;
+__device__ __forceinline__ void fused_gather(const ProbView& pv, const double* __restrict__ ysr,
+                                             const double* __restrict__ ysi, int a0, int b0,
+                                             bool diag, double (*Tr)[TE + 1], double (*Ti)[TE + 1],
+                                             double (*Xr)[TE + 1], double (*Xi)[TE + 1]) {
+  constexpr int NW = ETHREADS / 64, TPW = 2 * TE / NW, TQ = FUSE_TASKS_IN_FLIGHT;
+  static_assert(TPW * 8 == 64 && TPW % TQ == 0, "eight index slots per task fill a wave");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntask = diag ? TE : 2 * TE;
+  // this lane's index slot: entry k of task j
+  int e0 = 0, e1 = 0, idx = 0;
+  {
+    const int j = lane >> 3, k = lane & 7;
+    const int t = wave + NW * j;
+    const int row = t < TE ? b0 + t : a0 + t - TE;
+    if (t < ntask && row < pv.n) {
+      e0 = pv.h_ptr[row];
+      e1 = pv.h_ptr[row + 1];
+    }
+    if (e1 > e0) idx = pv.h_idx[min(e0 + k, e1 - 1)];
+  }
+  const int ld = pv.ld, cl = lane & 31;
+  const double* __restrict__ Yp = (lane >> 5) ? ysi : ysr;
+  const double sg = (double)pv.hsign;
+  const int jend = diag ? TPW / 2 : TPW;  // diagonal pairs: tasks w + 8 j < 32
+#pragma unroll
+  for (int j0 = 0; j0 < TPW; j0 += TQ) {
+    if (j0 >= jend) break;
+    double v[TQ][8];
+    const double* base[TQ];
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const int t = wave + NW * (j0 + q);
+      base[q] = Yp + (t < TE ? a0 : b0) + cl;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = __builtin_amdgcn_readlane(idx, 8 * (j0 + q) + k);
+        v[q][k] = base[q][(size_t)r * ld];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const int jq = j0 + q, t = wave + NW * jq;
+      const int f0 = __builtin_amdgcn_readlane(e0, 8 * jq);
+      const int f1 = __builtin_amdgcn_readlane(e1, 8 * jq);
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += f0 + k < f1 ? v[q][k] : 0.0;
+      for (int e = f0 + 8; e < f1; e += 8) {  // rows with more than eight neighbours
+        double u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = base[q][(size_t)pv.h_idx[min(e + k, f1 - 1)] * ld];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += e + k < f1 ? u[k] : 0.0;
+      }
+      const double val = sg * acc;
+      if (t < TE)
+        ((lane >> 5) ? Ti : Tr)[t][cl] = val;
+      else
+        ((lane >> 5) ? Xi : Xr)[t - TE][cl] = val;
+    }
+  }
+}
+
 // One tile pair {(I, J), (J, I)}, I <= J, of the right-hand side and its RK4
 // stage.  The state is Hermitian and L maps Hermitian to (bitwise) Hermitian,
 // so only (I, J) is evaluated: y_n, the accumulator and the anchor residual
@@ -140,6 +214,9 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
                                               double* __restrict__ partials, int tile) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
   __shared__ double Or[TE][TE + 1], Oi[TE][TE + 1];
+  constexpr bool FUSED = XS == XS_FUSED64;
+  // fused: X(I, J) is gathered into Or/Oi; each thread reads its elements
+  // there before it writes its outputs to the same places
   __shared__ double gs[TE];
   __shared__ double red[ETHREADS / 64];
   const int tid = threadIdx.x, tx = tid & (TE - 1), ty = tid / TE;
@@ -148,18 +225,52 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   tri_decode(tile, I, J);
   const int a0 = I * TE, b0 = J * TE;
   const bool diag = I == J;
+  const int b = b0 + tx;
+  const bool bin = b < n;
+
+  // All loads of this thread's four elements are issued before any store:
+  // outputs may alias inputs (y_n is updated in place at the last RK4 stage),
+  // so the compiler could not reorder them across the stores itself.
+  const bool need_yn = a.mode != EPI_RHS;
+  const bool need_acc = a.mode == EPI_S2 || a.mode == EPI_S3 || a.mode == EPI_S4;
+  double xa[EM], xb[EM], yr_[EM], yi_[EM], nr_[EM], ni_[EM], cr_[EM], ci_[EM], rr_[EM], ri_[EM];
+  auto load_state = [&](int m) {  // Y_s, anchor residual, y_n, accumulator at element m
+    const int ar = a0 + ty + ERS * m;
+    const size_t o = (size_t)ar * ld + b;
+    yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
+    if (bin && ar < n) {
+      yr_[m] = a.ysr[o];
+      yi_[m] = a.ysi[o];
+      if (a.rar) {
+        rr_[m] = a.rar[o];
+        ri_[m] = a.rai[o];
+      }
+    }
+    if (need_yn) {
+      nr_[m] = a.ynr[o];
+      ni_[m] = a.yni[o];
+    }
+    if (need_acc) {
+      cr_[m] = a.accr[o];
+      ci_[m] = a.acci[o];
+    }
+  };
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
+  if constexpr (FUSED) {
+    fused_gather(pv, a.ysr, a.ysi, a0, b0, diag, Tr, Ti, Or, Oi);
+  } else {
 #pragma unroll
-  for (int m = 0; m < EM; ++m) {
-    const int r = ty + ERS * m;
-    const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
-    if (XS != XS_DENSE32) {
-      Tr[r][tx] = a.xr[o];
-      Ti[r][tx] = a.xi[o];
-    } else {
-      Tr[r][tx] = (double)a.xfr[o];
-      Ti[r][tx] = (double)a.xfi[o];
+    for (int m = 0; m < EM; ++m) {
+      const int r = ty + ERS * m;
+      const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
+      if (XS != XS_DENSE32) {
+        Tr[r][tx] = a.xr[o];
+        Ti[r][tx] = a.xi[o];
+      } else {
+        Tr[r][tx] = (double)a.xfr[o];
+        Ti[r][tx] = (double)a.xfi[o];
+      }
     }
   }
   if (I == J) {  // gain of the jump terms on this tile's diagonal
@@ -205,47 +316,30 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   __syncthreads();
 
   const double w = a.omega, cw = 1.0 - a.omega;
-  const int b = b0 + tx;
-  const bool bin = b < n;
   const double hb = bin ? pv.h[b] : 0.0, db = bin ? pv.d[b] : 0.0;
   double ssum = 0.0, emax = 0.0;
   int sbad = 0;
   const int fstage = a.mode >= EPI_F1 ? a.mode - EPI_F1 + 1 : 0;  // Fehlberg stage 1..6
   const double hstep = fstage ? st->h : 0.0;
-  // All loads of this thread's four elements are issued before any store:
-  // outputs may alias inputs (y_n is updated in place at the last RK4 stage),
-  // so the compiler could not reorder them across the stores itself.
-  const bool need_yn = a.mode != EPI_RHS;
-  const bool need_acc = a.mode == EPI_S2 || a.mode == EPI_S3 || a.mode == EPI_S4;
-  double xa[EM], xb[EM], yr_[EM], yi_[EM], nr_[EM], ni_[EM], cr_[EM], ci_[EM], rr_[EM], ri_[EM];
 #pragma unroll
   for (int m = 0; m < EM; ++m) {
     const int ar = a0 + ty + ERS * m;
     const size_t o = (size_t)ar * ld + b;
-    xa[m] = xb[m] = yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
+    xa[m] = xb[m] = 0.0;
     if (bin && ar < n) {
-      if (XS != XS_DENSE32) {
+      if (FUSED) {  // X(I, J) from LDS (the diagonal block is Tr/Ti itself)
+        const int r = ty + ERS * m;
+        xa[m] = diag ? Tr[r][tx] : Or[r][tx];
+        xb[m] = diag ? Ti[r][tx] : Oi[r][tx];
+      } else if (XS != XS_DENSE32) {
         xa[m] = a.xr[o];
         xb[m] = a.xi[o];
       } else {
         xa[m] = (double)a.xfr[o];
         xb[m] = (double)a.xfi[o];
       }
-      yr_[m] = a.ysr[o];
-      yi_[m] = a.ysi[o];
-      if (a.rar) {
-        rr_[m] = a.rar[o];
-        ri_[m] = a.rai[o];
-      }
     }
-    if (need_yn) {
-      nr_[m] = a.ynr[o];
-      ni_[m] = a.yni[o];
-    }
-    if (need_acc) {
-      cr_[m] = a.accr[o];
-      ci_[m] = a.acci[o];
-    }
+    load_state(m);
   }
 #pragma unroll
   for (int m = 0; m < EM; ++m) {
@@ -502,6 +596,17 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
     k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
   if (st->stop || (a.gate && st->hold)) return;
   epilogue_tile<XS>(pv, a, st, partials, blockIdx.x);
+}
+
+// The fused form (the sparse product gathered inside the tile), also at six
+// waves per SIMD: with X sharing the output tiles it needs 34 KB of LDS, so
+// three workgroups fit per CU.  Two gathers of eight rows in flight per wave
+// keep it within 80 VGPRs; one more wave per SIMD would spill.
+__global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
+    k_epilogue_fused(ProbView pv, EpiArgs a, DevState* __restrict__ st,
+                     double* __restrict__ partials) {
+  if (st->stop || (a.gate && st->hold)) return;
+  epilogue_tile<XS_FUSED64>(pv, a, st, partials, blockIdx.x);
 }
 
 // Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
@@ -1105,6 +1210,8 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
     k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  else if (a.xkind == XS_FUSED64)
+    k_epilogue_fused<<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else
     return hipErrorInvalidValue;
   if (finish && reduces(a.mode)) k_finish<<<1, FOLD_THREADS, 0, s>>>(finish_job(pv, a, w));

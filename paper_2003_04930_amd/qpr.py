@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "QPR_OK", -1: "QPR_E_ARG", -2: "QPR_E_HIP", -3: "QPR_E_NOT_CO
 TELEPORT = {"paper_f": 0, "uniform": 1}
 HDIAG = {"zero": 0, "paper": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-PRODUCT = {"auto": 0, "dense": 1, "sparse": 2}
+PRODUCT = {"auto": 0, "dense": 1, "sparse": 2, "fused": 3}
 INTEGRATOR = {"rk4": 0, "rkf45": 1}
 
 # every symbol include/qpr.h declares
@@ -383,7 +383,8 @@ def rank(p):
 
 
 def time_kernels(P: Problem, omega, rho, prec="fp64", cfg=-1, reps=50):
-    """Mean ms per launch of (product, stage-1 epilogue), timed with HIP events."""
+    """Mean ms per launch of (product, RK4-stage epilogue over the four stages), timed with HIP
+    events; cfg -2 / -3 - v pick the sparse product (see qpr_time_kernels)."""
     rho = _planar_arg(rho, P.n)
     ws = workspace(P.n, prec)
     out = (C.c_double * 2)()

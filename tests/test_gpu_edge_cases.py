@@ -42,7 +42,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_rhs_and_steps_on_degenerate_graphs(Q, name, product):
     g = CASES[name]()
@@ -113,7 +113,7 @@ def n8192(Q):
     return Q.Problem.from_graph(g), rho, f(rho), O.rk4_ref(rho, f, 0.01, 1)
 
 
-@pytest.mark.parametrize("product", ["sparse", "dense"])
+@pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
 def test_rhs_and_stages_at_n8192(Q, n8192, product):
     """The largest size tested: the right-hand side and one RK4 step (all four
     stage kernels) against the oracle over every element."""

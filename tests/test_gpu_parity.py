@@ -72,7 +72,7 @@ def test_build_matches_oracle(Q, name, teleport, hdiag):
 
 
 # --------------------------------------------------------------------- rhs
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 @pytest.mark.parametrize("name", sorted(GRAPHS))
 @pytest.mark.parametrize("omega", [0.0, 0.35, 0.8, 1.0])
 def test_rhs_fp64_matches_oracle(Q, name, omega, product):
@@ -88,7 +88,7 @@ def test_rhs_fp64_matches_oracle(Q, name, omega, product):
 
 
 # -------------------------------------------------------------- RK4 steps
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 @pytest.mark.parametrize("name,steps", [("er16", 60), ("er70", 25), ("ba130", 12)])
 def test_rk4_steps_step_locked(Q, name, steps, product):
     g = GRAPHS[name]()
@@ -107,7 +107,7 @@ def test_rk4_steps_step_locked(Q, name, steps, product):
 
 
 # ---------------------------------------------------------- steady state
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 def test_steady_state_config1_matches_oracle(Q, product):
     g = GRAPHS["er16"]()
     P = Q.Problem.from_graph(g)
@@ -135,7 +135,7 @@ def test_steady_state_graph_and_chunking_do_not_change_result(Q, chunk, use_grap
     assert torch.equal(out.rho, ref.rho)
 
 
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 def test_steady_state_ba130_properties_and_oracle(Q, product):
     g = GRAPHS["ba130"]()
     P = Q.Problem.from_graph(g)
@@ -183,7 +183,7 @@ def test_error_paths(Q):
 
 
 # ------------------------------------------------------ Fehlberg RKF45
-@pytest.mark.parametrize("product", ["dense", "sparse"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
 def test_rkf45_attempts_match_oracle(Q, product):
     """The first attempts of the adaptive Fehlberg integration: same accepted
     and rejected counts and the same state as the oracle's RKF45."""
@@ -265,7 +265,7 @@ def test_rhs_full_size(Q, n, m):
     R = oracle_problem(g)
     rho = inputs.random_density(n, seed=1)
     want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.8)
-    for product in ("dense", "sparse"):
+    for product in ("dense", "sparse", "fused"):
         got = Q.to_complex(Q.rhs(P, 0.8, Q.planar(rho), product=product))
         assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
     # the H_off pattern the sparse product gathers through
@@ -299,6 +299,25 @@ def test_sparse_variants_bitwise_equal(Q, name):
         assert np.array_equal(outs[0], outs[v]), Q.SPARSE_VARIANTS[v]
     want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.5)
     assert np.max(np.abs(outs[0] - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("name", ["hub_isolated", "ba922"])
+def test_fused_epilogue_ragged_rows(Q, name):
+    """The fused epilogue's gathers on a 189-entry row, empty rows and a ragged
+    last tile: the right-hand side and one RK4 step match the oracle, and the
+    result is bitwise Hermitian."""
+    g = _hub_and_isolated() if name == "hub_isolated" else inputs.ba_digraph(922, 3, seed=0)
+    P = Q.Problem.from_graph(g)
+    R = oracle_problem(g)
+    rho = inputs.random_density(g.n, seed=13)
+    got = Q.to_complex(Q.rhs(P, 0.4, Q.planar(rho), product="fused"))
+    want = O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.4)
+    assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+    assert np.array_equal(got, got.conj().T)
+    x = Q.planar(rho)
+    Q.rk4_step(P, 0.4, 0.01, 1, x, product="fused")
+    want1 = O.rk4_ref(rho, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, 0.4), 0.01, 1)
+    assert np.max(np.abs(Q.to_complex(x) - want1)) < 1e-12
 
 
 def test_sparse_variant_out_of_range(Q):
