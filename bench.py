@@ -4,10 +4,12 @@ Workload (one "step" = one pass of the whole path over the batch): the
 scale-free directed graph N=922 (Barabasi-Albert m=3, random edge direction,
 10 % reciprocal, seed 0), Google damping 0.85, built on the GPU, then solved
 to ||L(rho)||_F < 1e-8 from rho0 = I/N with RK4 dt = 0.01 in FP64 at each of
-omega = 0.2, 0.5, 0.8, and ranked.  `value` is the throughput in solves per
-second over the timed steps (inputs resident in HBM; host readback of the
-device flag once per chunk is part of it); the mean time-to-steady-state per
-solve is `extra.seconds_per_solve_fp64`.
+omega = 0.2, 0.5, 0.8, and ranked; the three solves run concurrently, one
+stream each (qpr_steady_state_many; each is bitwise the single-system solve,
+and the sequential time is reported beside it).  `value` is the throughput in
+solves per second over the timed steps (inputs resident in HBM; host readback
+of the device flag once per chunk is part of it); the mean time-to-steady-state
+per solve is `extra.seconds_per_solve_fp64`.
 
 Also reported (same graph, same omegas): the paper's adaptive RKF45
 integrator, the accelerated solver (RKF45 from the learned, omega-blended
@@ -61,13 +63,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def solve_all(Q, P, prec, rho0_fn=None, product="auto"):
-    out = []
-    for w in OMEGAS:
-        r = Q.steady_state(P, w, DT, TOL, 400000, prec=prec, product=product,
-                           rho0=None if rho0_fn is None else rho0_fn(w))
-        out.append(r)
-    return out
+def solve_all(Q, P, prec, rho0_fn=None, product="auto", integrator="rk4"):
+    """The three omegas solved concurrently (qpr_steady_state_many: one stream
+    and host thread per omega, each bitwise the single-system solve)."""
+    rho0s = None if rho0_fn is None else [rho0_fn(w) for w in OMEGAS]
+    return Q.steady_state_many([(P, w) for w in OMEGAS], DT, TOL, 400000, prec=prec,
+                               rho0s=rho0s, product=product, integrator=integrator)
+
+
+def solve_sequential(Q, P):
+    return [Q.steady_state(P, w, DT, TOL, 400000) for w in OMEGAS]
 
 
 def cpu_baseline(g, gpu_steps):
@@ -118,10 +123,8 @@ def accelerated(Q, W, P, params, plain, plain_value, torch, np):
         W.warm_rho0(P, w, params)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = []
-    for w in OMEGAS:
-        rho0 = W.warm_rho0(P, w, params)
-        out.append(Q.steady_state(P, w, DT, TOL, 400000, rho0=rho0, integrator="rkf45"))
+    out = solve_all(Q, P, "fp64", rho0_fn=lambda w: W.warm_rho0(P, w, params),
+                    integrator="rkf45")
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / len(OMEGAS)
     err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(out, plain))
@@ -270,6 +273,17 @@ def main():
                           "residual": r.stats["residual"]} for w, r in zip(OMEGAS, results)}
     value = ms_per_step / 1e3 / len(OMEGAS)   # seconds per solve (time-to-steady-state)
     log(f"fp64: {value:.3f} s/solve, steps {steps}")
+    # the same three solves one after another on one stream, for comparison
+    torch.cuda.synchronize()
+    t0s = time.perf_counter()
+    seq = solve_sequential(Q, P)
+    torch.cuda.synchronize()
+    seq_value = (time.perf_counter() - t0s) / len(OMEGAS)
+    seq_same = all(bool(torch.equal(a.rho, b.rho)) and a.stats["steps"] == b.stats["steps"]
+                   for a, b in zip(seq, results))
+    del seq
+    log(f"fp64 sequential: {seq_value:.3f} s/solve, bitwise equal to the concurrent solves "
+        f"{seq_same}")
 
     # Kernels of the timed path, timed with HIP events on the solve's stream.
     # At this density the product is the sparse one (CSR gathers, k_spmm);
@@ -309,6 +323,9 @@ def main():
 
     extra = {"per_omega_fp64": per_omega, "build_seconds": t_build,
              "seconds_per_solve_fp64": value, "product": "sparse" if sparse else "dense",
+             "sequential_fp64": {"seconds_per_solve": seq_value,
+                                 "concurrency_speedup": seq_value / value,
+                                 "bitwise_equal": seq_same},
              "dense_product": {"us": gemm_ms * 1e3, "achieved_TFs": gemm_tf,
                                "peak_TFs": FP64_PEAK_TFLOPS, "frac": gemm_tf / FP64_PEAK_TFLOPS,
                                "flops_per_launch": flops},
@@ -326,7 +343,7 @@ def main():
     if not args.no_rkf45:
         # the paper's own integrator: adaptive Fehlberg 4(5), FP64, same tolerance
         t0f = time.perf_counter()
-        rf = [Q.steady_state(P, w, DT, TOL, 400000, integrator="rkf45") for w in OMEGAS]
+        rf = solve_all(Q, P, "fp64", integrator="rkf45")
         torch.cuda.synchronize()
         tf = (time.perf_counter() - t0f) / len(OMEGAS)
         errf = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rf, results))
@@ -439,7 +456,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"ba{N}-m{M_BA}-s0 FP64 steady state, omega in {list(OMEGAS)}, "
-                               f"dt={DT}, tol={TOL}, rho0=I/N; value = solves per second "
+                               f"dt={DT}, tol={TOL}, rho0=I/N, RK4, the three solves "
+                               f"concurrent on three streams; value = solves per second "
                                f"({'sparse' if sparse else 'dense'} product)",
                    "n": N, "omegas": list(OMEGAS), "tol": TOL, "dt": DT},
         "roofline": roofline,

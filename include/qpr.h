@@ -246,6 +246,33 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
                             const qpr_opts* opts, void* ws, size_t ws_bytes,
                             qpr_stream_t stream);
 
+/*
+ * `count` independent qpr_steady_state solves run concurrently: system k
+ * (problem probs[k] at omegas[k], state rhos[k]) on streams[k] with its own
+ * workspace ws[k] of ws_bytes[k] bytes, each driven by a host thread of its
+ * own (on the caller's current device).  Small systems leave most of the GPU
+ * idle between dependent launches; kernels of the other systems fill it.
+ * Every system computes exactly what qpr_steady_state computes on it (same
+ * kernels, same order: bitwise the same state, rank and step count).
+ *   probs, omegas, rhos, ranks, ws, ws_bytes, streams  HOST arrays [count];
+ *           ranks may be NULL, or hold NULL entries
+ *   stats   HOST qpr_stats[count] or NULL
+ *   streams must be distinct (two systems on one stream would serialise and
+ *           their workspaces must still differ); workspaces must not overlap
+ * Returns QPR_OK when every system returns QPR_OK, else the status of the
+ * lowest-numbered failing system, whose message qpr_last_error() gives
+ * (prefixed "system k: "); stats[k].status holds each system's own status.
+ * Errors: those of qpr_steady_state, and QPR_E_ARG (count < 1, NULL arrays,
+ * a repeated stream).  Returns when every system has finished.
+ */
+qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
+                                 const double* omegas, double dt, double tol,
+                                 int64_t max_steps, int32_t prec,
+                                 double* const* rhos, int32_t* const* ranks,
+                                 qpr_stats* stats, const qpr_opts* opts,
+                                 void* const* ws, const size_t* ws_bytes,
+                                 const qpr_stream_t* streams);
+
 /* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys)
  * with these options (NULL = defaults; opts->integrator = QPR_RKF45 adds each
  * system's Fehlberg stage planes).  0 for an invalid request. */

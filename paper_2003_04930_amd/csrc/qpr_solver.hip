@@ -8,6 +8,9 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "qpr_common.h"
@@ -729,6 +732,60 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = S;
   return result;
+}
+
+// One host thread per system, each running the single-system solve on its own
+// stream; the calling thread waits for all of them.  Error messages live in
+// thread-local storage, so each worker copies its own out.
+extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
+                                            const double* omegas, double dt, double tol,
+                                            int64_t max_steps, int32_t prec, double* const* rhos,
+                                            int32_t* const* ranks, qpr_stats* stats,
+                                            const qpr_opts* opts, void* const* ws,
+                                            const size_t* wsb, const qpr_stream_t* streams) {
+  clear_error();
+  if (count < 1) return fail(QPR_E_ARG, "count must be >= 1 (got %d)", count);
+  if (!probs || !omegas || !rhos || !ws || !wsb || !streams)
+    return fail(QPR_E_ARG, "probs, omegas, rhos, ws, ws_bytes and streams must not be NULL");
+  for (int k = 0; k < count; ++k)
+    for (int j = 0; j < k; ++j)
+      if (streams[j] == streams[k])
+        return fail(QPR_E_ARG, "systems %d and %d share a stream", j, k);
+  int dev = 0;
+  QPR_HIP(hipGetDevice(&dev));
+  std::vector<qpr_status> status(count, QPR_OK);
+  std::vector<std::string> msg(count);
+  std::vector<qpr_stats> local(count);
+  auto solve = [&](int k) {
+    if (hipSetDevice(dev) != hipSuccess) {
+      status[k] = QPR_E_HIP;
+      msg[k] = "hipSetDevice failed in the worker thread";
+      return;
+    }
+    status[k] = qpr_steady_state(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
+                                 ranks ? ranks[k] : nullptr, &local[k], opts, ws[k], wsb[k],
+                                 streams[k]);
+    local[k].status = status[k];
+    if (status[k] != QPR_OK) msg[k] = qpr_last_error();
+  };
+  // a system whose worker cannot be started runs on the calling thread
+  std::vector<std::thread> workers;
+  std::vector<int> here;
+  workers.reserve(count);
+  for (int k = 0; k < count; ++k) {
+    try {
+      workers.emplace_back(solve, k);
+    } catch (const std::system_error&) {
+      here.push_back(k);
+    }
+  }
+  for (int k : here) solve(k);
+  for (auto& t : workers) t.join();
+  if (stats)
+    for (int k = 0; k < count; ++k) stats[k] = local[k];
+  for (int k = 0; k < count; ++k)
+    if (status[k] != QPR_OK) return fail(status[k], "system %d: %s", k, msg[k].c_str());
+  return QPR_OK;
 }
 
 extern "C" qpr_status qpr_hub_counts(int32_t n, const double* p, double c, int32_t* counts,

@@ -32,7 +32,8 @@ INTEGRATOR = {"rk4": 0, "rkf45": 1}
 # every symbol include/qpr.h declares
 EXPORTS = (
     "qpr_problem_bytes", "qpr_build_google", "qpr_workspace_bytes", "qpr_rhs",
-    "qpr_rk4_step", "qpr_steady_state", "qpr_rank", "qpr_last_error", "qpr_version",
+    "qpr_rk4_step", "qpr_steady_state", "qpr_steady_state_many", "qpr_rank", "qpr_last_error",
+    "qpr_version",
     "qpr_time_kernels", "qpr_product_configs", "qpr_product_config_name",
     "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
     "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam", "qpr_autotune",
@@ -115,6 +116,8 @@ def lib():
         "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                    C.POINTER(qpr_opts), vp, sz, vp]),
+        "qpr_steady_state_many": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp,
+                                        C.POINTER(qpr_stats), C.POINTER(qpr_opts), vp, vp, vp]),
         "qpr_rank": (i32, [i32, vp, vp, vp]),
         "qpr_hub_counts": (i32, [i32, vp, dbl, vp, vp]),
         "qpr_time_kernels": (i32, [P, dbl, i32, i32, i32, vp, C.POINTER(C.c_double), vp, sz, vp]),
@@ -249,7 +252,10 @@ _ws_cache = {}
 
 
 def workspace(n, prec="fp64"):
-    key = (int(n), prec)
+    """The cached workspace for (n, prec) on the current stream.  Calls on one
+    stream run in order and may share it; each other stream gets its own, so
+    solves on concurrent streams never share scratch memory."""
+    key = (int(n), prec, _stream().value)
     ws = _ws_cache.get(key)
     if ws is None:
         ws = _ws_cache[key] = Workspace(n, prec)
@@ -361,6 +367,58 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
                                     _stream())
     _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
     return SolveResult(rho, rank, st.as_dict(), status)
+
+
+_stream_pool = []
+
+
+def _pool_streams(k):
+    """The first k streams of a pool kept for the life of the process (their
+    cached workspaces are reused from call to call)."""
+    torch = _torch()
+    while len(_stream_pool) < k:
+        _stream_pool.append(torch.cuda.Stream())
+    return _stream_pool[:k]
+
+
+def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0s=None,
+                      want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1,
+                      gemm_cfg=-1, allow_not_converged=False, product="auto", integrator="rk4",
+                      step_tol=1e-4, dt_max=0.0):
+    """Solve [(Problem, omega), ...] concurrently with qpr_steady_state_many, one
+    stream per system; each result is bitwise what steady_state returns."""
+    torch = _torch()
+    k = len(items)
+    streams = _pool_streams(k)
+    cur = torch.cuda.current_stream()
+    rhos, ranks, wss = [], [], []
+    for i, (P, _) in enumerate(items):
+        if rho0s is None or rho0s[i] is None:
+            r = torch.zeros((2, P.n, P.n), dtype=torch.float64, device="cuda")
+            r[0].diagonal().fill_(1.0 / P.n)
+        else:
+            r = _planar_arg(rho0s[i], P.n).clone()
+        rhos.append(r)
+        ranks.append(torch.empty(P.n, dtype=torch.int32, device="cuda") if want_rank else None)
+        with torch.cuda.stream(streams[i]):
+            wss.append(workspace(P.n, prec))
+    for s in streams:        # the initial states are written on the current stream
+        s.wait_stream(cur)
+    op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
+                   dt_max)
+    probs = (C.POINTER(qpr_problem) * k)(*[C.pointer(P.p) for P, _ in items])
+    omegas = (C.c_double * k)(*[float(w) for _, w in items])
+    rho_ptrs = (C.c_void_p * k)(*[r.data_ptr() for r in rhos])
+    rank_ptrs = (C.c_void_p * k)(*[(r.data_ptr() if r is not None else None) for r in ranks])
+    ws_ptrs = (C.c_void_p * k)(*[w.ptr for w in wss])
+    ws_bytes = (C.c_size_t * k)(*[w.nbytes for w in wss])
+    handles = (C.c_void_p * k)(*[s.cuda_stream for s in streams])
+    stats = (qpr_stats * k)()
+    status = lib().qpr_steady_state_many(k, probs, omegas, float(dt), float(tol), int(max_steps),
+                                         PREC[prec], rho_ptrs, rank_ptrs, stats, C.byref(op),
+                                         ws_ptrs, ws_bytes, handles)
+    _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
+    return [SolveResult(r, rk, st.as_dict(), st.status) for r, rk, st in zip(rhos, ranks, stats)]
 
 
 def hub_counts(p, c=10.0):

@@ -118,6 +118,19 @@ def test_solver_argument_errors_before_device_work():
     assert "built problem" in L.qpr_last_error().decode()
 
 
+def test_concurrent_solve_argument_errors_before_device_work():
+    L = _lib()
+    two = lambda t: (t * 2)()
+    probs, omegas = two(C.c_void_p), (C.c_double * 2)(0.5, 0.5)
+    rhos, ws, wsb = two(C.c_void_p), two(C.c_void_p), (C.c_size_t * 2)(1, 1)
+    args = (0.01, 1e-8, 10, 0, rhos, None, None, None, ws, wsb)
+    assert L.qpr_steady_state_many(0, probs, omegas, *args, two(C.c_void_p)) == qpr.QPR_E_ARG
+    assert L.qpr_steady_state_many(2, None, omegas, *args, two(C.c_void_p)) == qpr.QPR_E_ARG
+    same = (C.c_void_p * 2)(4096, 4096)
+    assert L.qpr_steady_state_many(2, probs, omegas, *args, same) == qpr.QPR_E_ARG
+    assert "share a stream" in L.qpr_last_error().decode()
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(qpr, "_lib", None)
     monkeypatch.setattr(qpr, "LIB_PATH", str(tmp_path / "absent.so"))

@@ -1,0 +1,84 @@
+"""Concurrent single-system solves (qpr_steady_state_many): one stream and one
+host thread per system, the single-system kernels unchanged, so every system
+must reproduce its sequential qpr_steady_state solve bit for bit (state, rank,
+step count), which the oracle pins in test_gpu_parity.py; the oracle is also
+checked directly on the smallest system here.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_04930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2003_04930_amd import qpr
+    qpr.lib()
+    assert torch.cuda.is_available()
+    return qpr
+
+
+def _same(a, b):
+    assert torch.equal(a.rho, b.rho)
+    assert a.stats["steps"] == b.stats["steps"]
+    assert a.stats["rejected"] == b.stats["rejected"]
+    if a.rank is not None:
+        assert torch.equal(a.rank, b.rank)
+
+
+@pytest.mark.parametrize("integrator,prec", [("rk4", "fp64"), ("rkf45", "fp64"),
+                                             ("rk4", "fp32")])
+def test_many_equals_sequential_solves(Q, integrator, prec):
+    gs = [inputs.er_digraph(16, 0.2, seed=0), inputs.er_digraph(70, 0.06, seed=3),
+          inputs.ba_digraph(130, 3, seed=1), inputs.ba_digraph(300, 2, seed=5)]
+    probs = [Q.Problem.from_graph(g) for g in gs]
+    items = [(probs[0], 0.8), (probs[1], 0.3), (probs[2], 0.6), (probs[3], 0.9), (probs[2], 0.2)]
+    kw = dict(tol=1e-9, max_steps=200000, prec=prec, integrator=integrator, chunk=16)
+    many = Q.steady_state_many(items, **kw)
+    for (P, w), got in zip(items, many):
+        _same(got, Q.steady_state(P, w, **kw))
+        assert got.stats["converged"] == 1 and got.status == Q.QPR_OK
+
+
+def test_many_matches_oracle_and_warm_starts(Q):
+    g = inputs.er_digraph(16, 0.2, seed=0)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    omegas = (0.8, 0.5)
+    rho0 = inputs.random_density(16, seed=2)
+    out = Q.steady_state_many([(P, w) for w in omegas], tol=1e-10, max_steps=100000,
+                              rho0s=[None, Q.planar(rho0)])
+    for w, r0, got in zip(omegas, (np.eye(16) / 16, rho0), out):
+        f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, w)
+        want, nsteps, _ = O.steady_ref(r0, f, 0.01, 1e-10, 100000)
+        assert got.stats["steps"] == nsteps
+        assert np.max(np.abs(Q.to_complex(got.rho) - want)) < 1e-10
+
+
+def test_many_n922_three_omegas(Q):
+    """The N = 922 workload's three solves run together equal the sequential ones."""
+    P = Q.Problem.from_graph(inputs.ba_digraph(922, 3, seed=0))
+    items = [(P, w) for w in (0.2, 0.5, 0.8)]
+    many = Q.steady_state_many(items, tol=1e-6, max_steps=400000)
+    for (_, w), got in zip(items, many):
+        _same(got, Q.steady_state(P, w, tol=1e-6, max_steps=400000))
+
+
+def test_many_reports_the_failing_system(Q):
+    P = Q.Problem.from_graph(inputs.er_digraph(40, 0.1, seed=1))
+    with pytest.raises(Q.QprError) as e:
+        Q.steady_state_many([(P, 0.5), (P, 1.5), (P, 0.7)], tol=1e-8)
+    assert e.value.status == Q.QPR_E_ARG and "system 1" in str(e.value)
+    # not converged within the budget: the last states come back, flagged per system
+    out = Q.steady_state_many([(P, 0.5), (P, 0.7)], tol=1e-12, max_steps=50,
+                              allow_not_converged=True)
+    for (_, w), got in zip([(P, 0.5), (P, 0.7)], out):
+        assert got.status == Q.QPR_E_NOT_CONVERGED
+        ref = Q.steady_state(P, w, tol=1e-12, max_steps=50, allow_not_converged=True)
+        assert torch.equal(got.rho, ref.rho)
