@@ -147,7 +147,8 @@ def accelerated(Q, W, P, params, plain, plain_value, torch, np):
 def target_rows(Q, W, P, params, plain, plain_value, torch, np):
     """The three omegas of the workload solved together by qpr_batch_solve from
     the warm start: FP32 mixed precision (sparse FP32 products, FP64 folds and
-    judge) with RK4, and FP64 RKF45.  Inference is inside the timed region."""
+    judge) with RK4, and FP64 RKF45; then the mixed solve as three concurrent
+    single-system solves.  Inference is inside the timed region."""
     items = [(P, w) for w in OMEGAS]
     out = {}
     for name, kw in (("batch_mixed_fp32_warm", dict(prec="fp32")),
@@ -170,6 +171,23 @@ def target_rows(Q, W, P, params, plain, plain_value, torch, np):
                      "order_violations_beyond_2maxdrho": viol}
         log(f"{name}: {t:.3f} s/solve ({plain_value / t:.1f}x), max|drho| {err:.1e}, "
             f"ranking identical {exact}")
+    # the same mixed-precision solve from the warm start with the three omegas
+    # on three streams (single-system kernels, run concurrently)
+    t0 = time.perf_counter()
+    rm = solve_all(Q, P, "fp32", rho0_fn=lambda w: W.warm_rho0(P, w, params))
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / len(OMEGAS)
+    err = max(float((a.rho - b.rho).abs().max()) for a, b in zip(rm, plain))
+    exact = all(bool(torch.equal(a.rank, b.rank)) for a, b in zip(rm, plain))
+    viol = sum(tie_aware_rank_check(b.rho[0].diagonal().cpu().numpy(), a.rank.cpu().numpy(),
+                                    2 * err, np) for a, b in zip(rm, plain))
+    out["concurrent_mixed_fp32_warm"] = {
+        "seconds_per_solve": t, "speedup_vs_plain_fp64": plain_value / t,
+        "steps": [r.stats["steps"] for r in rm], "folds": [r.stats["folds"] for r in rm],
+        "residuals": [r.stats["residual"] for r in rm], "max_abs_drho_vs_plain": err,
+        "ranking_identical": exact, "order_violations_beyond_2maxdrho": viol}
+    log(f"concurrent_mixed_fp32_warm: {t:.3f} s/solve ({plain_value / t:.1f}x), "
+        f"max|drho| {err:.1e}, ranking identical {exact}")
     return out
 
 

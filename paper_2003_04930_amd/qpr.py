@@ -105,6 +105,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise QprError(QPR_E_HIP, f"{LIB_PATH} is missing; build it with "
                                   "`python -m paper_2003_04930_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch loaded (the
+    # one that owns the device memory and streams passed in), not to a second
+    # copy found on the library path
+    _torch()
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
     P = C.POINTER(qpr_problem)
