@@ -252,8 +252,12 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
  * workspace ws[k] of ws_bytes[k] bytes, each driven by a host thread of its
  * own (on the caller's current device).  Small systems leave most of the GPU
  * idle between dependent launches; kernels of the other systems fill it.
- * Every system computes exactly what qpr_steady_state computes on it (same
- * kernels, same order: bitwise the same state, rank and step count).
+ * Every system computes exactly what qpr_steady_state computes on it (bitwise
+ * the same state, rank and step count).  With QPR_PRODUCT_AUTO, FP64 stages
+ * that a lone solve would give the sparse product + epilogue take the fused
+ * epilogue (QPR_PRODUCT_FUSED, the same sums in the same order) while two or
+ * more systems are still running, the faster form when other systems' kernels
+ * run beside it; a system left running alone goes back to the two kernels.
  *   probs, omegas, rhos, ranks, ws, ws_bytes, streams  HOST arrays [count];
  *           ranks may be NULL, or hold NULL entries
  *   stats   HOST qpr_stats[count] or NULL

@@ -1,6 +1,7 @@
 // Host drivers of the C ABI: right-hand side, fixed RK4 steps and the
 // steady-state solve (plain FP64, or defect correction with a low-precision
 // product judged in FP64).
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -524,20 +525,28 @@ extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt
 namespace {
 
 // Run chunks of `chunk` steps (eager or as a replayed graph) until the device
-// control block says stop.  Returns the final host copy of the block.
+// control block says stop.  Returns the final host copy of the block.  With
+// `alt` set, each chunk is either enqueue_chunk or alt->enqueue, as
+// alt->choose() says just before it is launched (both captured once).
+struct AltChunk {
+  std::function<hipError_t(hipStream_t)> enqueue;
+  std::function<bool()> choose;
+};
 qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chunk,
                       DevState* dev_st, bool use_graph, hipStream_t s, DevState* final_state,
-                      long long* chunks_run) {
+                      long long* chunks_run, const AltChunk* alt = nullptr) {
   DevState* hs = pinned_states();
   if (!hs) return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr, exec_alt = nullptr;
+  hipGraph_t graph = nullptr, graph_alt = nullptr;
   hipStream_t cs = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   qpr_status rc = QPR_OK;
   auto cleanup = [&]() {
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
+    if (exec_alt) hipGraphExecDestroy(exec_alt);
+    if (graph_alt) hipGraphDestroy(graph_alt);
     if (cs) hipStreamDestroy(cs);
     for (auto& e : ev)
       if (e) hipEventDestroy(e);
@@ -559,11 +568,21 @@ qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chun
     QPR_HIP_C(e);
     QPR_HIP_C(e2);
     QPR_HIP_C(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (alt) {
+      QPR_HIP_C(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipError_t ea = alt->enqueue(cs);
+      hipError_t ea2 = hipStreamEndCapture(cs, &graph_alt);
+      QPR_HIP_C(ea);
+      QPR_HIP_C(ea2);
+      QPR_HIP_C(hipGraphInstantiate(&exec_alt, graph_alt, nullptr, nullptr, 0));
+    }
   }
   QPR_HIP_C(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   QPR_HIP_C(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   auto launch = [&](int slot) -> hipError_t {
-    hipError_t e = use_graph ? hipGraphLaunch(exec, s) : enqueue_chunk(s);
+    const bool a = alt && alt->choose();
+    hipError_t e = use_graph ? hipGraphLaunch(a ? exec_alt : exec, s)
+                             : (a ? alt->enqueue(s) : enqueue_chunk(s));
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(&hs[slot], dev_st, sizeof(DevState), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
@@ -588,10 +607,16 @@ qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chun
 
 }  // namespace
 
-extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt, double tol,
-                                       int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
-                                       qpr_stats* stats, const qpr_opts* opts, void* ws,
-                                       size_t wsb, qpr_stream_t stream) {
+// The single-system solve.  `running` (NULL for a lone solve) counts the
+// systems of a concurrent qpr_steady_state_many call still running: while it
+// is two or more, the FP64 stages that AUTO gives the two-kernel sparse stage
+// take the fused epilogue instead (bitwise the same sums; with the other
+// systems' kernels beside it, the one launch per stage is the faster one),
+// and a system left running alone goes back to the two kernels.
+static qpr_status steady_state_impl(const qpr_problem* P, double omega, double dt, double tol,
+                                    int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
+                                    qpr_stats* stats, const qpr_opts* opts, void* ws, size_t wsb,
+                                    qpr_stream_t stream, const std::atomic<int>* running) {
   const auto t0 = std::chrono::steady_clock::now();
   clear_error();
   Ws w;
@@ -614,6 +639,17 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   const int n = P->n, ld = P->ld;
   qpr_stats S{};
   qpr_status result = QPR_OK;
+  const bool switch_fused = running && o.product == QPR_PRODUCT_AUTO &&
+                            x_source(P, o.product, OP_F64) == XS_SPARSE64;
+  const int product = switch_fused ? QPR_PRODUCT_SPARSE : o.product;
+  AltChunk alt;
+  const AltChunk* altp = nullptr;
+  auto set_alt = [&](std::function<hipError_t(hipStream_t)> f) {
+    if (!switch_fused) return;
+    alt.enqueue = std::move(f);
+    alt.choose = [running]() { return running->load(std::memory_order_relaxed) >= 2; };
+    altp = &alt;
+  };
 
   const bool graph = o.use_graph != 0;
   DevState fs{};
@@ -630,14 +666,17 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
     QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_RKF, s));
     QPR_HIP(launch_state_rkf(w.st, std::min(dt, hmax), hmax, o.step_tol, s));
     QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
-    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
-      for (int k = 0; k < o.chunk; ++k) {
-        hipError_t e = enqueue_rkf_attempt(P, w, pv, omega, o.gemm_cfg, o.product, q);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
+    auto chunk_of = [&](int pr) {
+      return [&, pr](hipStream_t q) -> hipError_t {
+        for (int k = 0; k < o.chunk; ++k) {
+          hipError_t e = enqueue_rkf_attempt(P, w, pv, omega, o.gemm_cfg, pr, q);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      };
     };
-    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    set_alt(chunk_of(QPR_PRODUCT_FUSED));
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
     if (st != QPR_OK) return st;
     S.steps = fs.accepted;
     S.rejected = fs.rejected;
@@ -648,15 +687,18 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   } else if (prec == QPR_FP64) {
     QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_PLAIN, s));
     QPR_HIP(launch_pad_in(rho, n, ld, w.yn_r, w.yn_i, w.p_n, s));
-    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
-      for (int k = 0; k < o.chunk; ++k) {
-        hipError_t e =
-            enqueue_step(P, w, pv, omega, dt, OP_F64, o.gemm_cfg, o.product, CHK_PLAIN, false, q);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
+    auto chunk_of = [&](int pr) {
+      return [&, pr](hipStream_t q) -> hipError_t {
+        for (int k = 0; k < o.chunk; ++k) {
+          hipError_t e =
+              enqueue_step(P, w, pv, omega, dt, OP_F64, o.gemm_cfg, pr, CHK_PLAIN, false, q);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      };
     };
-    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    set_alt(chunk_of(QPR_PRODUCT_FUSED));
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
     if (st != QPR_OK) return st;
     S.steps = fs.converged ? fs.conv_step : fs.step;
     S.rhs_evals = 4 * S.steps + 1;
@@ -680,29 +722,32 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
       if (e == hipSuccess && xk == OP_BF16X3) e = launch_fill(w.sl, 6 * plane * 2, q);
       return e;
     };
-    auto fold_judge = [&](hipStream_t q, bool first) -> hipError_t {
+    auto fold_judge = [&](hipStream_t q, bool first, int pr) -> hipError_t {
       hipError_t e = hipSuccess;
       if (!first) e = launch_axpy_planes(w.an_r, w.an_i, w.yn_r, w.yn_i, 1.0, n, ld, w.p_a, w.st, q);
       if (e == hipSuccess && o.renorm) e = launch_trace(w.p_a, n, w.st, q);
       if (e == hipSuccess && o.renorm) e = launch_scale_planes(w.an_r, w.an_i, w.p_a, n, ld, w.st, q);
       if (e == hipSuccess)
         e = enqueue_rhs(P, w, pv, omega, w.an_r, w.an_i, w.p_a, w.ra_r, w.ra_i, OP_F64,
-                        o.gemm_cfg, o.product, CHK_JUDGE, q);
+                        o.gemm_cfg, pr, CHK_JUDGE, q);
       if (e == hipSuccess) e = reset_delta(q);
       return e;
     };
     QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_DELTA, s));
     QPR_HIP(launch_pad_in(rho, n, ld, w.an_r, w.an_i, w.p_a, s));
-    QPR_HIP(fold_judge(s, true));
-    auto chunk_fn = [&](hipStream_t q) -> hipError_t {
-      for (int k = 0; k < o.fold_every; ++k) {
-        hipError_t e =
-            enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, o.product, CHK_DELTA, true, q);
-        if (e != hipSuccess) return e;
-      }
-      return fold_judge(q, false);
+    QPR_HIP(fold_judge(s, true, product));
+    auto chunk_of = [&](int pr) {
+      return [&, pr](hipStream_t q) -> hipError_t {
+        for (int k = 0; k < o.fold_every; ++k) {
+          hipError_t e =
+              enqueue_step(P, w, pv, omega, dt, xk, o.gemm_cfg, pr, CHK_DELTA, true, q);
+          if (e != hipSuccess) return e;
+        }
+        return fold_judge(q, false, pr);
+      };
     };
-    st = run_chunks(chunk_fn, w.st, graph, s, &fs, &chunks);
+    set_alt(chunk_of(QPR_PRODUCT_FUSED));
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
     if (st != QPR_OK) return st;
     S.steps = fs.converged ? fs.conv_step : fs.step;
     S.folds = fs.folds;
@@ -734,6 +779,14 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
   return result;
 }
 
+extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt, double tol,
+                                       int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
+                                       qpr_stats* stats, const qpr_opts* opts, void* ws,
+                                       size_t wsb, qpr_stream_t stream) {
+  return steady_state_impl(P, omega, dt, tol, max_steps, prec, rho, rank, stats, opts, ws, wsb,
+                           stream, nullptr);
+}
+
 // One host thread per system, each running the single-system solve on its own
 // stream; the calling thread waits for all of them.  Error messages live in
 // thread-local storage, so each worker copies its own out.
@@ -756,15 +809,18 @@ extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* co
   std::vector<qpr_status> status(count, QPR_OK);
   std::vector<std::string> msg(count);
   std::vector<qpr_stats> local(count);
+  std::atomic<int> running(count);
   auto solve = [&](int k) {
     if (hipSetDevice(dev) != hipSuccess) {
       status[k] = QPR_E_HIP;
       msg[k] = "hipSetDevice failed in the worker thread";
+      running.fetch_sub(1, std::memory_order_relaxed);
       return;
     }
-    status[k] = qpr_steady_state(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
-                                 ranks ? ranks[k] : nullptr, &local[k], opts, ws[k], wsb[k],
-                                 streams[k]);
+    status[k] = steady_state_impl(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
+                                  ranks ? ranks[k] : nullptr, &local[k], opts, ws[k], wsb[k],
+                                  streams[k], &running);
+    running.fetch_sub(1, std::memory_order_relaxed);
     local[k].status = status[k];
     if (status[k] != QPR_OK) msg[k] = qpr_last_error();
   };

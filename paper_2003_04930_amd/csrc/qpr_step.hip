@@ -137,7 +137,8 @@ __host__ __device__ constexpr int tri_tiles(int t) { return t * (t + 1) / 2; }
 // vector load (lane 8 j + k: entry k of task j) and are broadcast from there,
 // so only the row loads are on the critical path; rows with more than eight
 // neighbours finish with groups of eight read through the index array.  Each
-// row is summed in CSR order.
+// row is summed in the order of the separate sparse product (eight partials,
+// fixed tree), so the two give bitwise the same X.
 constexpr int FUSE_TASKS_IN_FLIGHT = 2;
 __device__ __forceinline__ void fused_gather(const ProbView& pv, const double* __restrict__ ysr,
                                              const double* __restrict__ ysi, int a0, int b0,
@@ -183,17 +184,21 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const double* _
       const int jq = j0 + q, t = wave + NW * jq;
       const int f0 = __builtin_amdgcn_readlane(e0, 8 * jq);
       const int f1 = __builtin_amdgcn_readlane(e1, 8 * jq);
-      double acc = 0.0;
+      // entry e into partial (e - e0) % 8, partials added in the fixed tree:
+      // bitwise the sum the separate sparse product forms
+      double* acc = v[q];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc += f0 + k < f1 ? v[q][k] : 0.0;
+      for (int k = 0; k < 8; ++k) acc[k] = 0.0 + (f0 + k < f1 ? acc[k] : 0.0);
       for (int e = f0 + 8; e < f1; e += 8) {  // rows with more than eight neighbours
         double u[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) u[k] = base[q][(size_t)pv.h_idx[min(e + k, f1 - 1)] * ld];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc += e + k < f1 ? u[k] : 0.0;
+        for (int k = 0; k < 8; ++k) acc[k] += e + k < f1 ? u[k] : 0.0;
       }
-      const double val = sg * acc;
+      const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+      const double val = sg * sum;
       if (t < TE)
         ((lane >> 5) ? Ti : Tr)[t][cl] = val;
       else

@@ -320,6 +320,29 @@ def test_fused_epilogue_ragged_rows(Q, name):
     assert np.max(np.abs(Q.to_complex(x) - want1)) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["er70", "ba130", "hub_isolated", "ba922"])
+def test_fused_equals_sparse_bitwise(Q, name):
+    """The fused epilogue sums each gathered row in the separate sparse
+    product's order, so the right-hand side, RK4 steps and RKF45 attempts are
+    bitwise those of the two-kernel stage."""
+    g = (_hub_and_isolated() if name == "hub_isolated" else
+         inputs.ba_digraph(922, 3, seed=0) if name == "ba922" else GRAPHS[name]())
+    P = Q.Problem.from_graph(g)
+    rho = Q.planar(inputs.random_density(g.n, seed=17))
+    a = Q.rhs(P, 0.45, rho, product="sparse")
+    b = Q.rhs(P, 0.45, rho, product="fused")
+    assert torch.equal(a, b)
+    xa, xb = rho.clone(), rho.clone()
+    Q.rk4_step(P, 0.45, 0.01, 3, xa, product="sparse")
+    Q.rk4_step(P, 0.45, 0.01, 3, xb, product="fused")
+    assert torch.equal(xa, xb)
+    ra = Q.steady_state(P, 0.7, 0.01, 1e-14, 20, integrator="rkf45", product="sparse",
+                        allow_not_converged=True, chunk=7)
+    rb = Q.steady_state(P, 0.7, 0.01, 1e-14, 20, integrator="rkf45", product="fused",
+                        allow_not_converged=True, chunk=7)
+    assert torch.equal(ra.rho, rb.rho) and ra.stats["steps"] == rb.stats["steps"]
+
+
 def test_sparse_variant_out_of_range(Q):
     g = GRAPHS["er16"]()
     P = Q.Problem.from_graph(g)
