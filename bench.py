@@ -46,9 +46,10 @@ BF16_PEAK_TFLOPS = 2500.0
 # WRITE_SIZE (x1.00) passes, the factors calibrated on a 256 MiB copy; valid
 # for the stage kernels in the source with this sha256 prefix only (the
 # summary with the commands: profiles/sparse_stage_hbm_counters_n922_n4096.md)
-COUNTERS_SRC = ("paper_2003_04930_amd/csrc/qpr_step.hip", "c6e64debaa317ac2")
-TRAFFIC_N922 = {"epilogue": (16485.76 * 2.0 + 19992.66) * 1024.0,
-                "spmm": (7374.43 * 2.0 + 13830.0) * 1024.0}
+COUNTERS_SRC = ("paper_2003_04930_amd/csrc/qpr_step.hip", "caf367ba83e36191")
+TRAFFIC_N922 = {"epilogue": (16487.5 * 2.0 + 19992.7) * 1024.0,
+                "spmm": (7369.5 * 2.0 + 13830.0) * 1024.0,
+                "fused": (35228.7 * 2.0 + 19992.7) * 1024.0}
 
 
 def measured_traffic(kernel):
@@ -56,7 +57,9 @@ def measured_traffic(kernel):
     import hashlib
     with open(os.path.join(ROOT, COUNTERS_SRC[0]), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
-    return TRAFFIC_N922[kernel] if digest.startswith(COUNTERS_SRC[1]) else None
+    if not digest.startswith(COUNTERS_SRC[1]):
+        return None
+    return TRAFFIC_N922.get(kernel)
 
 
 def log(msg):
@@ -303,14 +306,24 @@ def main():
     log(f"fp64 sequential: {seq_value:.3f} s/solve, bitwise equal to the concurrent solves "
         f"{seq_same}")
 
-    # Kernels of the timed path, timed with HIP events on the solve's stream.
-    # At this density the product is the sparse one (CSR gathers, k_spmm);
-    # each stage is k_spmm + the fused epilogue.  The dense MFMA product is
-    # timed too.
+    # Kernels of the timed path, timed with HIP events on the stream they run
+    # on, one kernel at a time.  At this density the product is the sparse one:
+    # while two or more of the concurrent solves run, a stage is one fused
+    # epilogue launch (k_epilogue_fused, the gathers inside the tile kernel);
+    # the solve left running alone takes k_spmm + k_epilogue per stage.  The
+    # dense MFMA product is timed too.
     rho_ss = results[-1].rho
     sparse = P.p.nnz_h < 0.05 * N * N
     sp_ms, epi_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", cfg=-2, reps=200)
+    _, fused_ms = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64",
+                                 cfg=-3 - len(Q.SPARSE_VARIANTS), reps=200)
     gemm_ms, _ = Q.time_kernels(P, OMEGAS[-1], rho_ss, prec="fp64", reps=100)
+    # stages of each kind in the timed path: a solve's steps run fused while
+    # another solve still runs (up to the second-longest step count), the rest
+    # of the longest solve as two kernels
+    srt = sorted(steps)
+    fused_steps = sum(min(k, srt[-2]) for k in srt)
+    alone_steps = srt[-1] - srt[-2]
     ld = P.ld
     # algorithmic bytes per epilogue launch, unique data per element, the
     # mean over the four RK4 stages (X 16 B read in full; Y_s, y_n, acc on the
@@ -320,19 +333,32 @@ def main():
     #   sparse product: each gathered row of Y read once from HBM (16 B/elem),
     #   X written (16 B/elem); the nnz_H-fold re-reads hit the caches
     sp_bytes = 32.0 * N * N
+    #   fused epilogue: the epilogue's bytes with the X read (16 B) and the
+    #   upper-triangle read of Y_s (8 B) replaced by Y_s gathered in full
+    #   (16 B): stage 1 40, stages 2-3 56, stage 4 48 -> 50 B per element
+    fused_bytes = 50.0 * N * N
     flops = 4.0 * N ** 3                       # dense product: two real N x N x N products
     gemm_tf = flops / (gemm_ms * 1e-3) / 1e12
     epi_gbs = epi_bytes / (epi_ms * 1e-3) / 1e9
     sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9
+    fused_gbs = fused_bytes / (fused_ms * 1e-3) / 1e9
     log(f"stage: spmm {sp_ms * 1e3:.1f} us ({sp_gbs:.0f} GB/s), epilogue {epi_ms * 1e3:.1f} us "
-        f"({epi_gbs:.0f} GB/s); dense product {gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s)")
+        f"({epi_gbs:.0f} GB/s), fused epilogue {fused_ms * 1e3:.1f} us ({fused_gbs:.0f} GB/s); "
+        f"dense product {gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s)")
     if sparse:
-        dom = ("k_epilogue (fused RHS + RK4 stage)", epi_gbs, epi_bytes, epi_ms, "epilogue") \
-            if epi_ms >= sp_ms else ("k_spmm (sparse commutator product)", sp_gbs, sp_bytes, sp_ms,
-                                     "spmm")
+        # the dominant kernel: the largest launch count x launch time
+        cands = [("k_epilogue_fused (sparse gathers + RHS + RK4 stage)", fused_gbs, fused_bytes,
+                  fused_ms, "fused", 4 * fused_steps),
+                 ("k_epilogue (fused RHS + RK4 stage)", epi_gbs, epi_bytes, epi_ms, "epilogue",
+                  4 * alone_steps),
+                 ("k_spmm (sparse commutator product)", sp_gbs, sp_bytes, sp_ms, "spmm",
+                  4 * alone_steps)]
+        dom = max(cands, key=lambda c: c[3] * c[5])
         roofline = {"bound": "hbm", "achieved": dom[1], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": dom[1] / HBM_PEAK_GBS, "traffic": measured_traffic(dom[4]),
-                    "kernel": dom[0], "bytes_per_launch": dom[2], "us_per_launch": dom[3] * 1e3}
+                    "kernel": dom[0], "bytes_per_launch": dom[2], "us_per_launch": dom[3] * 1e3,
+                    "launches_in_timed_step": dom[5],
+                    "launch_time": "one kernel at a time, HIP events on its stream"}
     else:
         roofline = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": gemm_tf / FP64_PEAK_TFLOPS, "traffic": None,
@@ -351,6 +377,9 @@ def main():
                           "frac": epi_gbs / HBM_PEAK_GBS, "bytes_per_launch": epi_bytes},
              "spmm": {"us": sp_ms * 1e3, "achieved_GBs": sp_gbs,
                       "frac": sp_gbs / HBM_PEAK_GBS, "bytes_per_launch": sp_bytes},
+             "fused_epilogue": {"us": fused_ms * 1e3, "achieved_GBs": fused_gbs,
+                                "frac": fused_gbs / HBM_PEAK_GBS, "bytes_per_launch": fused_bytes},
+             "stages_in_timed_step": {"fused": 4 * fused_steps, "two_kernel": 4 * alone_steps},
              "nnz_h": int(P.p.nnz_h), "ld": ld}
 
     params = None
