@@ -197,9 +197,11 @@ struct EpiArgs {
 
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w,
                        const double* yr, const double* yi, int gate, hipStream_t s);
-// finish = false leaves a reducing stage's partials unfolded (kernel timing)
+// finish = false leaves a reducing stage's partials unfolded (kernel timing,
+// or a finishing step carried by the next launch); `carry` (fused epilogue
+// only) is the previous stage's finishing step, run as one extra workgroup
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
-                           bool finish = true);
+                           bool finish = true, const FinishJob* carry = nullptr);
 hipError_t launch_pad_in(const double* rho, int n, int ld, double* r, double* i,
                          double* p, hipStream_t s);
 hipError_t launch_pad_out(const double* r, const double* i, int n, int ld,

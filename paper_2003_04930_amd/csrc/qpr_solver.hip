@@ -281,7 +281,8 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
   const bool sparse = use_sparse(P, product, xk);
   const int xs = x_source(P, product, xk);
   const bool fused = xs == XS_FUSED64;
-  // with the sparse product the stage-2 launch carries stage 1's finishing step
+  // with the sparse product the stage-2 launch (product, or fused epilogue)
+  // carries stage 1's finishing step
   FinishJob pending{};
   for (int k = 0; k < 4; ++k) {
     const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, xs, check, gate, with_ra);
@@ -291,8 +292,8 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
                          k == 1 ? &pending : nullptr);
       if (e != hipSuccess) return e;
     }
-    const bool carry = sparse && !fused && k == 0;
-    e = launch_epilogue(pv, a, w, s, !carry);
+    const bool carry = sparse && k == 0;
+    e = launch_epilogue(pv, a, w, s, !carry, fused && k == 1 ? &pending : nullptr);
     if (e != hipSuccess) return e;
     if (carry) pending = finish_job(pv, a, w);
   }
@@ -435,8 +436,8 @@ static hipError_t enqueue_rkf_attempt(const qpr_problem* P, const Ws& w, const P
                          st == 1 ? &pending : nullptr);
       if (e != hipSuccess) return e;
     }
-    const bool carry = sparse && !fused && st == 0;
-    e = launch_epilogue(pv, a, w, s, !carry);
+    const bool carry = sparse && st == 0;
+    e = launch_epilogue(pv, a, w, s, !carry, fused && st == 1 ? &pending : nullptr);
     if (e != hipSuccess) return e;
     if (carry) pending = finish_job(pv, a, w);
   }

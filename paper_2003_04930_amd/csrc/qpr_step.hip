@@ -79,14 +79,16 @@ __device__ __forceinline__ void tile_partials(double my_sum, int my_bad, double 
 // loads in flight), the four combined as (0+1)+(2+3), then a fixed shuffle
 // tree per wave and the four waves in order.  Every finisher -- the finishing
 // kernels and the sparse-product launches that carry a finishing workgroup --
-// runs it with 256 threads, so they agree bit for bit.
+// runs it with 256 threads, so they agree bit for bit; in a larger workgroup
+// the threads past the first 256 load nothing and only join the barriers.
 constexpr int FOLD_THREADS = 256;
 __device__ __forceinline__ void fold_partials(const double* partials, int nb, double& tot,
                                               int& bad, double& mx) {
   __shared__ double rs[FOLD_THREADS / 64], rb[FOLD_THREADS / 64], rm[FOLD_THREADS / 64];
   const int t = threadIdx.x;
+  const bool act = t < FOLD_THREADS;
   double a[4] = {0.0, 0.0, 0.0, 0.0}, bb = 0.0, mm = 0.0;
-  int i = t;
+  int i = act ? t : nb;
   for (; i + 3 * FOLD_THREADS < nb; i += 4 * FOLD_THREADS) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -106,7 +108,7 @@ __device__ __forceinline__ void fold_partials(const double* partials, int nb, do
     }
   const double acc = (a[0] + a[1]) + (a[2] + a[3]);
   const double ws = wave_sum_d(acc), wb = wave_max_d(bb), wm = wave_max_d(mm);
-  if ((t & 63) == 0) {
+  if (act && (t & 63) == 0) {
     rs[t >> 6] = ws;
     rb[t >> 6] = wb;
     rm[t >> 6] = wm;
@@ -127,6 +129,15 @@ __device__ __forceinline__ void tri_decode(int k, int& I, int& J) {
   I = k - j * (j + 1) / 2;
 }
 __host__ __device__ constexpr int tri_tiles(int t) { return t * (t + 1) / 2; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (bid % 8).  This
+// renumbering gives XCD x one contiguous run of the nb logical indices (a
+// bijection of [0, nb)), so neighbouring work items share its L2.
+__device__ __forceinline__ int xcd_contiguous(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
 
 // The fused sparse product: the two 32 x 32 blocks of X = H_off Y that tile
 // pair (I, J) needs, gathered through the CSR of H_off straight into LDS.
@@ -607,11 +618,29 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
 // waves per SIMD: with X sharing the output tiles it needs 34 KB of LDS, so
 // three workgroups fit per CU.  Two gathers of eight rows in flight per wave
 // keep it within 80 VGPRs; one more wave per SIMD would spill.
+//
+// It may carry the previous stage's finishing step as workgroup 0 (f.nb > 0),
+// all 512 threads taking part.  The tiles then run beside it: a stop it sets
+// is seen by some tiles of this launch and not others, which is harmless
+// because the stages that follow stage 1 write only the next stage's inputs
+// (y_n is written last, by stage 4 or the RKF45 commit, both gated), and the
+// only control value they read, the RKF45 step size, changes at stage 6 only.
+// With `xcd` set the tile pairs are renumbered so that each XCD takes one
+// contiguous run of them: tile pairs are ordered by column block J, and the
+// X(I, J) half of the gathers reads Y's block J only, so that slice stays in
+// one L2 (fewer fetched bytes; at N = 4096 and above it costs more than it
+// saves).
 __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue_fused(ProbView pv, EpiArgs a, DevState* __restrict__ st,
-                     double* __restrict__ partials) {
+                     double* __restrict__ partials, FinishJob f, int xcd) {
+  const int extra = f.nb > 0;
+  if (extra && blockIdx.x == 0) {
+    run_finish(f);
+    return;
+  }
   if (st->stop || (a.gate && st->hold)) return;
-  epilogue_tile<XS_FUSED64>(pv, a, st, partials, blockIdx.x);
+  const int nb = gridDim.x - extra, bid = blockIdx.x - extra;
+  epilogue_tile<XS_FUSED64>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
 }
 
 // Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
@@ -776,11 +805,6 @@ __device__ __forceinline__ void spmm_cm_group(const ProbView& pv, const double* 
   }
 }
 
-__device__ __forceinline__ int spmm_xcd_remap(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int x = bid & 7, k = bid >> 3;
-  return x * q + (x < r ? x : r) + k;
-}
 
 // The row-major and FP32 product launches may carry the finishing step of
 // the previous stage as one extra workgroup, the first one dispatched
@@ -796,7 +820,7 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
               double* __restrict__ xr, double* __restrict__ xi, const DevState* __restrict__ st,
               int gate, FinishJob) {
   if (st->stop || (gate && st->hold)) return;
-  spmm_cm_group<W, RPW>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x, gridDim.x));
+  spmm_cm_group<W, RPW>(pv, yr, yi, xr, xi, xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
 __global__ void __launch_bounds__(2 * SP_COLS)
@@ -880,7 +904,7 @@ __global__ void __launch_bounds__(64 * SP_WAVES)
     return;
   }
   if (st->stop || (gate && st->hold)) return;
-  spmm_f32_group<W>(pv, yr, yi, xr, xi, spmm_xcd_remap(blockIdx.x - extra, gridDim.x - extra));
+  spmm_f32_group<W>(pv, yr, yi, xr, xi, xcd_contiguous(blockIdx.x - extra, gridDim.x - extra));
 }
 
 // One row-major item (row a, 128-column chunk) of the sparse product for the
@@ -1206,19 +1230,23 @@ FinishJob finish_job(const ProbView& pv, const EpiArgs& a, const Ws& w) {
 }
 
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
-                           bool finish) {
+                           bool finish, const FinishJob* carry) {
   const int grid = tri_tiles(pv.ld / TE);
   if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
+  if (carry && a.xkind != XS_FUSED64) return hipErrorInvalidValue;
   if (a.xkind == XS_DENSE64)
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_DENSE32)
     k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else if (a.xkind == XS_FUSED64)
-    k_epilogue_fused<<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else
+  else if (a.xkind == XS_FUSED64) {
+    const FinishJob f = carry ? *carry : FinishJob{};
+    k_epilogue_fused<<<grid + (f.nb > 0 ? 1 : 0), ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f,
+                                                                   pv.ld < 4096 ? 1 : 0);
+  } else {
     return hipErrorInvalidValue;
+  }
   if (finish && reduces(a.mode)) k_finish<<<1, FOLD_THREADS, 0, s>>>(finish_job(pv, a, w));
   return hipGetLastError();
 }
