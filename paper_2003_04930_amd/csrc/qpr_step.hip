@@ -1345,6 +1345,8 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
     k_epilogue_batch<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else if (xsource == XS_SPARSE64)
     k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else if (xsource == XS_FUSED64)  // sparse gathers inside the tile kernel
+    k_epilogue_batch<XS_FUSED64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else
     return hipErrorInvalidValue;
   if (finish) k_finish_batch<<<256, FOLD_THREADS, 0, s>>>(args, sys_list, nsys);

@@ -31,7 +31,7 @@ def small_family():
     return gs
 
 
-@pytest.mark.parametrize("product", ["sparse", "dense"])
+@pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
 def test_fp64_batch_equals_single_solves(Q, product):
     gs = small_family()[:4]
     probs = [Q.Problem.from_graph(g) for g in gs]
@@ -45,7 +45,7 @@ def test_fp64_batch_equals_single_solves(Q, product):
         assert torch.equal(out.ranks[k], ref.rank)
 
 
-@pytest.mark.parametrize("product", ["sparse", "dense"])
+@pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
 def test_rkf45_batch_equals_single_solves(Q, product):
     """Each system keeps its own Fehlberg step size and control; the batched
     kernels reproduce the single adaptive solves bit for bit."""
@@ -79,7 +79,7 @@ def test_batch_graph_replay_equals_eager(Q):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("product", ["sparse", "dense"])
+@pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
 def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product):
     gs = small_family()
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.1, 0.9)]
