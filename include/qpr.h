@@ -161,15 +161,16 @@ typedef enum {
  * the state, sums in FP64, X rounded to FP32); QPR_BF16X3 is always dense. */
 typedef enum {
   QPR_PRODUCT_AUTO = 0,   /* sparse when H_off is below 5 % dense, else dense; the sparse
-                             choice is FUSED for FP64 stages from a padded size of 4096 on,
-                             in qpr_batch_solve, and in qpr_steady_state_many while two or
-                             more systems run */
+                             choice is FUSED for the FP32 steps of the mixed solve, and for
+                             FP64 stages from a padded size of 4096 on, in qpr_batch_solve,
+                             and in qpr_steady_state_many while two or more systems run */
   QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
   QPR_PRODUCT_SPARSE = 2, /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
   QPR_PRODUCT_FUSED = 3   /* the same gathers inside the epilogue: each tile pair gathers the two
                              32 x 32 blocks of X it needs into LDS, so X never goes to HBM and a
-                             stage is one launch; bitwise the SPARSE stage.  FP64 stages only
-                             (the FP32 product of the mixed solve stays separate) */
+                             stage is one launch; bitwise the SPARSE stage.  The FP32 steps
+                             of the mixed solve gather the FP32 copy of the state the same way
+                             (X rounded once to FP32, as the separate FP32 product) */
 } qpr_product;
 
 /* ------------------------------------------------------------------ build */
@@ -299,8 +300,8 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  * the FP32 copy of delta, or FP32 MFMA tiles -- with the FP64 fold-and-judge
  * defect correction of qpr_steady_state, judged every chunk); the product
  * follows opts->product, decided on probs[0]'s density for the whole batch
- * (with AUTO the FP64 sparse stages run as fused epilogues: the gathers in
- * the tile kernel, one launch per stage).
+ * (with AUTO the sparse stages, FP64 and FP32, run as fused epilogues: the
+ * gathers in the tile kernel, one launch per stage).
  * The dense-product tile configuration is tuned on this batch's own work list
  * unless opts->gemm_cfg >= 0.
  *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are

@@ -169,12 +169,13 @@ enum XSource {
   XS_DENSE64 = 0,   // FP64 X written by the dense product
   XS_DENSE32 = 1,   // FP32 X written by a low-precision dense product
   XS_SPARSE64 = 2,  // FP64 X written by the sparse product (k_spmm)
-  XS_FUSED64 = 3    // FP64 X gathered inside the epilogue tile (no product launch)
+  XS_FUSED64 = 3,   // FP64 X gathered inside the epilogue tile (no product launch)
+  XS_FUSED32 = 4    // the same from the FP32 copy of Y_s (xfr/xfi), X rounded to FP32
 };
 
 struct EpiArgs {
   const double *xr, *xi;      // FP64 X (OP_F64)
-  const float *xfr, *xfi;     // FP32 X (OP_F32 / OP_BF16X3)
+  const float *xfr, *xfi;     // FP32 X (OP_F32 / OP_BF16X3); XS_FUSED32: FP32 copy of Y_s
   const double *ysr, *ysi;    // stage input Y_s
   const double* ps;           // diag of Y_s
   const double *ynr, *yni;    // y_n

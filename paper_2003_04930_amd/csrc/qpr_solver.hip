@@ -59,14 +59,21 @@ static bool use_sparse(const qpr_problem* P, int product, int xk) {
 // Where the epilogue takes X from: the FP32 X of a low-precision product, the
 // FP64 X a separate product launch wrote (sparse or dense), or the epilogue's
 // own gathers (fused: no product launch).
-// AUTO takes the fused epilogue from a padded size of 4096 on: there a stage
-// is 13 % faster than product + epilogue; at 922 and 2048 the two kernels win
-// (the fused tile pairs run their gathers and the epilogue back to back, with
-// too few workgroups per CU to hide either).
+// AUTO takes the FP64 fused epilogue from a padded size of 4096 on: there a
+// stage is 13 % faster than product + epilogue; at 922 and 2048 the two
+// kernels win when a solve runs alone (the fused tile pairs run their gathers
+// and the epilogue back to back, with too few workgroups per CU to hide
+// either).  The FP32 steps of the mixed solve take the fused form at every
+// size: it gathers half the bytes (N = 922 solve 0.546 against 0.568 s,
+// N = 4096 stage 314 against 349 us).
 static int x_source(const qpr_problem* P, int product, int xk) {
-  if (xk != OP_F64) return XS_DENSE32;
+  if (xk == OP_BF16X3) return XS_DENSE32;
+  const bool sparse = use_sparse(P, product, xk);
+  if (xk == OP_F32)
+    return sparse && (product == QPR_PRODUCT_FUSED || product == QPR_PRODUCT_AUTO) ? XS_FUSED32
+                                                                                  : XS_DENSE32;
   if (product == QPR_PRODUCT_FUSED) return XS_FUSED64;
-  if (!use_sparse(P, product, xk)) return XS_DENSE64;
+  if (!sparse) return XS_DENSE64;
   return product == QPR_PRODUCT_AUTO && P->ld >= 4096 ? XS_FUSED64 : XS_SPARSE64;
 }
 
@@ -269,6 +276,16 @@ static EpiArgs rk4_stage_args(const Ws& w, int k, double omega, double dt, int x
   a.cdt = sg.cdt;
   a.mode = EPI_S1 + k;
   a.xkind = xs;
+  if (xs == XS_FUSED32) {
+    // no FP32 X: the X planes hold the second FP32 state copy; stage k
+    // gathers from one copy and writes the other (lo at even stages), so lo
+    // again holds the copy of y_n after stage 4
+    float *in_r = k % 2 ? w.xf_r : w.lo_r, *in_i = k % 2 ? w.xf_i : w.lo_i;
+    a.xfr = in_r;
+    a.xfi = in_i;
+    a.lor = k % 2 ? w.lo_r : w.xf_r;
+    a.loi = k % 2 ? w.lo_i : w.xf_i;
+  }
   a.check = k == 0 ? check : CHK_NONE;
   a.gate = gate;
   return a;
@@ -280,9 +297,10 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
   const int gate = check == CHK_DELTA ? 1 : 0;
   const bool sparse = use_sparse(P, product, xk);
   const int xs = x_source(P, product, xk);
-  const bool fused = xs == XS_FUSED64;
+  const bool fused = xs == XS_FUSED64 || xs == XS_FUSED32;
   // with the sparse product the stage-2 launch (product, or fused epilogue)
-  // carries stage 1's finishing step
+  // carries stage 1's finishing step; not a gated fused launch, whose tiles
+  // would have to see the hold that step may set
   FinishJob pending{};
   for (int k = 0; k < 4; ++k) {
     const EpiArgs a = rk4_stage_args(w, k, omega, dt, xk, xs, check, gate, with_ra);
@@ -292,7 +310,8 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
                          k == 1 ? &pending : nullptr);
       if (e != hipSuccess) return e;
     }
-    const bool carry = sparse && k == 0;
+    const bool carry = sparse && k == 0 && !(fused && gate);
+    // (pending is empty when stage 1 finished on its own: no extra workgroup)
     e = launch_epilogue(pv, a, w, s, !carry, fused && k == 1 ? &pending : nullptr);
     if (e != hipSuccess) return e;
     if (carry) pending = finish_job(pv, a, w);
@@ -310,7 +329,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
     hipError_t e = launch_to_lowp(xk, inr, ini, P->n, P->ld, w, s);
     if (e != hipSuccess) return e;
   }
-  if (xs != XS_FUSED64) {
+  if (xs != XS_FUSED64 && xs != XS_FUSED32) {
     hipError_t e = launch_product(P, w, pv, xk, cfg, sparse, inr, ini, 0, s);
     if (e != hipSuccess) return e;
   }
@@ -327,6 +346,10 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
   a.omega = omega;
   a.mode = EPI_RHS;
   a.xkind = xs;
+  if (xs == XS_FUSED32) {  // gathers from the FP32 copy of the input
+    a.xfr = w.lo_r;
+    a.xfi = w.lo_i;
+  }
   a.check = check;
   return launch_epilogue(pv, a, w, s);
 }
@@ -642,7 +665,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
   qpr_status result = QPR_OK;
   const bool switch_fused = running && o.product == QPR_PRODUCT_AUTO &&
                             x_source(P, o.product, OP_F64) == XS_SPARSE64;
-  const int product = switch_fused ? QPR_PRODUCT_SPARSE : o.product;
+  const int product = o.product;
   AltChunk alt;
   const AltChunk* altp = nullptr;
   auto set_alt = [&](std::function<hipError_t(hipStream_t)> f) {
@@ -887,10 +910,14 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   // v = the number of variants: the fused epilogue (no product launch)
   const bool sparse = cfg <= -2 && xk != OP_BF16X3;
   const int spv = cfg <= -3 ? -3 - cfg : -1;
-  const bool fused = sparse && xk == OP_F64 && spv == spmm_num_variants();
+  const bool fused = sparse && spv == spmm_num_variants();
   if (sparse && spv > spmm_num_variants() - (fused ? 0 : 1))
     return fail(QPR_E_ARG, "no such sparse-product variant");
-  const int xs = fused ? XS_FUSED64 : xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
+  const int xs = fused ? (xk == OP_F64 ? XS_FUSED64 : XS_FUSED32)
+                       : xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
+  // the FP32 fused stages gather from both FP32 copies in turn (the X planes
+  // hold the second one)
+  if (fused && xk == OP_F32) QPR_HIP(launch_fill(w.xf_r, 2 * (size_t)P->ld * P->ld * 4, s));
   HipEvent evh[3];
   for (auto& e : evh) QPR_HIP(hipEventCreate(&e.h));
   hipEvent_t ev[3] = {evh[0].h, evh[1].h, evh[2].h};

@@ -150,9 +150,12 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nb) {
 // neighbours finish with groups of eight read through the index array.  Each
 // row is summed in the order of the separate sparse product (eight partials,
 // fixed tree), so the two give bitwise the same X.
+// T = float: the rows come from the FP32 copy of Y_s, summed in FP64 in the
+// same order and rounded once to FP32, as the separate FP32 product does.
 constexpr int FUSE_TASKS_IN_FLIGHT = 2;
-__device__ __forceinline__ void fused_gather(const ProbView& pv, const double* __restrict__ ysr,
-                                             const double* __restrict__ ysi, int a0, int b0,
+template <typename T>
+__device__ __forceinline__ void fused_gather(const ProbView& pv, const T* __restrict__ ysr,
+                                             const T* __restrict__ ysi, int a0, int b0,
                                              bool diag, double (*Tr)[TE + 1], double (*Ti)[TE + 1],
                                              double (*Xr)[TE + 1], double (*Xi)[TE + 1]) {
   constexpr int NW = ETHREADS / 64, TPW = 2 * TE / NW, TQ = FUSE_TASKS_IN_FLIGHT;
@@ -172,14 +175,14 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const double* _
     if (e1 > e0) idx = pv.h_idx[min(e0 + k, e1 - 1)];
   }
   const int ld = pv.ld, cl = lane & 31;
-  const double* __restrict__ Yp = (lane >> 5) ? ysi : ysr;
+  const T* __restrict__ Yp = (lane >> 5) ? ysi : ysr;
   const double sg = (double)pv.hsign;
   const int jend = diag ? TPW / 2 : TPW;  // diagonal pairs: tasks w + 8 j < 32
 #pragma unroll
   for (int j0 = 0; j0 < TPW; j0 += TQ) {
     if (j0 >= jend) break;
     double v[TQ][8];
-    const double* base[TQ];
+    const T* base[TQ];
 #pragma unroll
     for (int q = 0; q < TQ; ++q) {
       const int t = wave + NW * (j0 + q);
@@ -187,7 +190,7 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const double* _
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int r = __builtin_amdgcn_readlane(idx, 8 * (j0 + q) + k);
-        v[q][k] = base[q][(size_t)r * ld];
+        v[q][k] = (double)base[q][(size_t)r * ld];
       }
     }
 #pragma unroll
@@ -203,13 +206,15 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const double* _
       for (int e = f0 + 8; e < f1; e += 8) {  // rows with more than eight neighbours
         double u[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) u[k] = base[q][(size_t)pv.h_idx[min(e + k, f1 - 1)] * ld];
+        for (int k = 0; k < 8; ++k)
+          u[k] = (double)base[q][(size_t)pv.h_idx[min(e + k, f1 - 1)] * ld];
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] += e + k < f1 ? u[k] : 0.0;
       }
       const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
                          ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-      const double val = sg * sum;
+      double val = sg * sum;
+      if constexpr (sizeof(T) == 4) val = (double)(float)val;
       if (t < TE)
         ((lane >> 5) ? Ti : Tr)[t][cl] = val;
       else
@@ -230,7 +235,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
                                               double* __restrict__ partials, int tile) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
   __shared__ double Or[TE][TE + 1], Oi[TE][TE + 1];
-  constexpr bool FUSED = XS == XS_FUSED64;
+  constexpr bool FUSED = XS == XS_FUSED64 || XS == XS_FUSED32;
   // fused: X(I, J) is gathered into Or/Oi; each thread reads its elements
   // there before it writes its outputs to the same places
   __shared__ double gs[TE];
@@ -273,8 +278,10 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   };
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
-  if constexpr (FUSED) {
-    fused_gather(pv, a.ysr, a.ysi, a0, b0, diag, Tr, Ti, Or, Oi);
+  if constexpr (XS == XS_FUSED32) {
+    fused_gather<float>(pv, a.xfr, a.xfi, a0, b0, diag, Tr, Ti, Or, Oi);
+  } else if constexpr (FUSED) {
+    fused_gather<double>(pv, a.ysr, a.ysi, a0, b0, diag, Tr, Ti, Or, Oi);
   } else {
 #pragma unroll
     for (int m = 0; m < EM; ++m) {
@@ -630,6 +637,7 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
 // X(I, J) half of the gathers reads Y's block J only, so that slice stays in
 // one L2 (fewer fetched bytes; at N = 4096 and above it costs more than it
 // saves).
+template <int XS>
 __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue_fused(ProbView pv, EpiArgs a, DevState* __restrict__ st,
                      double* __restrict__ partials, FinishJob f, int xcd) {
@@ -640,7 +648,7 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
   }
   if (st->stop || (a.gate && st->hold)) return;
   const int nb = gridDim.x - extra, bid = blockIdx.x - extra;
-  epilogue_tile<XS_FUSED64>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
+  epilogue_tile<XS>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
 }
 
 // Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
@@ -1233,17 +1241,20 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
                            bool finish, const FinishJob* carry) {
   const int grid = tri_tiles(pv.ld / TE);
   if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
-  if (carry && a.xkind != XS_FUSED64) return hipErrorInvalidValue;
+  if (carry && a.xkind != XS_FUSED64 && a.xkind != XS_FUSED32) return hipErrorInvalidValue;
   if (a.xkind == XS_DENSE64)
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_DENSE32)
     k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else if (a.xkind == XS_FUSED64) {
+  else if (a.xkind == XS_FUSED64 || a.xkind == XS_FUSED32) {
     const FinishJob f = carry ? *carry : FinishJob{};
-    k_epilogue_fused<<<grid + (f.nb > 0 ? 1 : 0), ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f,
-                                                                   pv.ld < 4096 ? 1 : 0);
+    const int g = grid + (f.nb > 0 ? 1 : 0), xcd = pv.ld < 4096 ? 1 : 0;
+    if (a.xkind == XS_FUSED64)
+      k_epilogue_fused<XS_FUSED64><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
+    else
+      k_epilogue_fused<XS_FUSED32><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
   } else {
     return hipErrorInvalidValue;
   }
@@ -1347,6 +1358,8 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
     k_epilogue_batch<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else if (xsource == XS_FUSED64)  // sparse gathers inside the tile kernel
     k_epilogue_batch<XS_FUSED64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else if (xsource == XS_FUSED32)
+    k_epilogue_batch<XS_FUSED32><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else
     return hipErrorInvalidValue;
   if (finish) k_finish_batch<<<256, FOLD_THREADS, 0, s>>>(args, sys_list, nsys);

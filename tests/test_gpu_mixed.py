@@ -27,7 +27,8 @@ def Q():
     return qpr
 
 
-@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "fused"), ("fp32", "dense"),
+                                          ("bf16x3", "dense")])
 @pytest.mark.parametrize("n,m,omega", [(70, 2, 0.3), (130, 3, 0.8), (922, 3, 0.5)])
 def test_lowp_rhs_error_bound(Q, prec, product, n, m, omega):
     g = inputs.ba_digraph(n, m, seed=n)
@@ -44,7 +45,8 @@ def test_lowp_rhs_error_bound(Q, prec, product, n, m, omega):
     assert np.array_equal(got, got.conj().T)
 
 
-@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "fused"), ("fp32", "dense"),
+                                          ("bf16x3", "dense")])
 def test_mixed_steady_state_matches_oracle(Q, prec, product):
     g = inputs.ba_digraph(130, 3, seed=1)
     P = Q.Problem.from_graph(g)
@@ -74,7 +76,8 @@ def test_mixed_steady_state_matches_oracle(Q, prec, product):
                 assert pos[i] < pos[j]
 
 
-@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "dense"), ("bf16x3", "dense")])
+@pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "fused"), ("fp32", "dense"),
+                                          ("bf16x3", "dense")])
 def test_mixed_n922_against_fp64_gpu(Q, prec, product):
     g = inputs.ba_digraph(922, 3, seed=0)
     P = Q.Problem.from_graph(g)
@@ -123,3 +126,24 @@ def test_every_dense_tile_configuration(Q, prec):
         outs.append(got)
     for name, got in zip(names[1:], outs[1:]):
         assert np.array_equal(got, outs[0]), name
+
+
+@pytest.mark.parametrize("name,n,m", [("ba130", 130, 3), ("ba922", 922, 3)])
+def test_fp32_fused_equals_fp32_sparse_bitwise(Q, name, n, m):
+    """The fused FP32 stage gathers the FP32 state copy, sums in FP64 in the
+    separate FP32 product's order and rounds X once to FP32, alternating its
+    two FP32 copies: right-hand side, RK4 steps and the defect-corrected
+    steady state are bitwise those of the two-kernel FP32 stage."""
+    P = Q.Problem.from_graph(inputs.ba_digraph(n, m, seed=0))
+    rho = Q.planar(inputs.random_density(n, seed=23))
+    assert torch.equal(Q.rhs(P, 0.6, rho, prec="fp32", product="sparse"),
+                       Q.rhs(P, 0.6, rho, prec="fp32", product="fused"))
+    xa, xb = rho.clone(), rho.clone()
+    Q.rk4_step(P, 0.6, 0.01, 5, xa, prec="fp32", product="sparse")
+    Q.rk4_step(P, 0.6, 0.01, 5, xb, prec="fp32", product="fused")
+    assert torch.equal(xa, xb)
+    tol = 1e-8 if n > 200 else 1e-9
+    a = Q.steady_state(P, 0.7, 0.01, tol, 400000, prec="fp32", product="sparse", fold_every=50)
+    b = Q.steady_state(P, 0.7, 0.01, tol, 400000, prec="fp32", product="fused", fold_every=50)
+    assert torch.equal(a.rho, b.rho)
+    assert a.stats["steps"] == b.stats["steps"] and a.stats["folds"] == b.stats["folds"]
