@@ -250,35 +250,40 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
                             qpr_stream_t stream);
 
 /*
- * `count` independent qpr_steady_state solves run concurrently: system k
- * (problem probs[k] at omegas[k], state rhos[k]) on streams[k] with its own
- * workspace ws[k] of ws_bytes[k] bytes, each driven by a host thread of its
- * own (on the caller's current device).  Small systems leave most of the GPU
- * idle between dependent launches; kernels of the other systems fill it.
- * Every system computes exactly what qpr_steady_state computes on it (bitwise
- * the same state, rank and step count).  With QPR_PRODUCT_AUTO, FP64 stages
- * that a lone solve would give the sparse product + epilogue take the fused
- * epilogue (QPR_PRODUCT_FUSED, the same sums in the same order) while two or
- * more systems are still running, the faster form when other systems' kernels
- * run beside it; a system left running alone goes back to the two kernels.
- *   probs, omegas, rhos, ranks, ws, ws_bytes, streams  HOST arrays [count];
- *           ranks may be NULL, or hold NULL entries
+ * `count` independent qpr_steady_state solves run concurrently by a pool of
+ * `nworkers` host threads (on the caller's current device): worker w solves
+ * on streams[w] with workspace ws[w], taking the next unsolved system (index
+ * order) whenever it is free, so min(nworkers, systems left) run at once.
+ * Small systems leave most of the GPU idle between dependent launches;
+ * kernels of the other systems fill it.  Every system computes exactly what
+ * qpr_steady_state computes on it (bitwise the same state, rank and step
+ * count).  With QPR_PRODUCT_AUTO, FP64 stages that a lone solve would give the
+ * sparse product + epilogue take the fused epilogue (QPR_PRODUCT_FUSED, the
+ * same sums in the same order) while two or more systems run, the faster
+ * form when other systems' kernels run beside it; a system left running
+ * alone goes back to the two kernels.
+ *   probs, omegas, rhos, ranks  HOST arrays [count]; rhos[k] device planar
+ *           2*n_k*n_k FP64 (in: rho0, out: steady state); ranks may be NULL
+ *           or hold NULL entries
  *   stats   HOST qpr_stats[count] or NULL
- *   streams must be distinct (two systems on one stream would serialise and
- *           their workspaces must still differ); workspaces must not overlap
+ *   nworkers  1..64 (more than count is allowed; count are used)
+ *   ws, ws_bytes, streams  HOST arrays [nworkers]: distinct streams, and
+ *           non-overlapping 256-byte-aligned workspaces of at least
+ *           qpr_workspace_bytes(largest n, prec) bytes each
  * Returns QPR_OK when every system returns QPR_OK, else the status of the
  * lowest-numbered failing system, whose message qpr_last_error() gives
  * (prefixed "system k: "); stats[k].status holds each system's own status.
- * Errors: those of qpr_steady_state, and QPR_E_ARG (count < 1, NULL arrays,
- * a repeated stream).  Returns when every system has finished.
+ * Errors: those of qpr_steady_state, QPR_E_ARG (count < 1, nworkers out of
+ * range, NULL arrays, a repeated stream), QPR_E_WORKSPACE (a workspace too
+ * small for the largest system).  Returns when every system has finished.
  */
 qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
                                  const double* omegas, double dt, double tol,
                                  int64_t max_steps, int32_t prec,
                                  double* const* rhos, int32_t* const* ranks,
                                  qpr_stats* stats, const qpr_opts* opts,
-                                 void* const* ws, const size_t* ws_bytes,
-                                 const qpr_stream_t* streams);
+                                 int32_t nworkers, void* const* ws,
+                                 const size_t* ws_bytes, const qpr_stream_t* streams);
 
 /* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys)
  * with these options (NULL = defaults; opts->integrator = QPR_RKF45 adds each

@@ -631,16 +631,26 @@ qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chun
 
 }  // namespace
 
-// The single-system solve.  `running` (NULL for a lone solve) counts the
-// systems of a concurrent qpr_steady_state_many call still running: while it
-// is two or more, the FP64 stages that AUTO gives the two-kernel sparse stage
-// take the fused epilogue instead (bitwise the same sums; with the other
-// systems' kernels beside it, the one launch per stage is the faster one),
-// and a system left running alone goes back to the two kernels.
+// Systems of a qpr_steady_state_many call not yet finished, and its workers:
+// min of the two is how many run at once.
+struct Concurrency {
+  std::atomic<int> remaining{0};
+  int workers = 1;
+  int in_flight() const {
+    return std::min(remaining.load(std::memory_order_relaxed), workers);
+  }
+};
+
+// The single-system solve.  `conc` is NULL for a lone solve; in a concurrent
+// call, while two or more systems run, the FP64 stages that AUTO gives the
+// two-kernel sparse stage take the fused epilogue instead (bitwise the same
+// sums; with the other systems' kernels beside it, the one launch per stage
+// is the faster one), and a system left running alone goes back to the two
+// kernels.
 static qpr_status steady_state_impl(const qpr_problem* P, double omega, double dt, double tol,
                                     int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
                                     qpr_stats* stats, const qpr_opts* opts, void* ws, size_t wsb,
-                                    qpr_stream_t stream, const std::atomic<int>* running) {
+                                    qpr_stream_t stream, const Concurrency* conc) {
   const auto t0 = std::chrono::steady_clock::now();
   clear_error();
   Ws w;
@@ -663,7 +673,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
   const int n = P->n, ld = P->ld;
   qpr_stats S{};
   qpr_status result = QPR_OK;
-  const bool switch_fused = running && o.product == QPR_PRODUCT_AUTO &&
+  const bool switch_fused = conc && conc->workers >= 2 && o.product == QPR_PRODUCT_AUTO &&
                             x_source(P, o.product, OP_F64) == XS_SPARSE64;
   const int product = o.product;
   AltChunk alt;
@@ -671,7 +681,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
   auto set_alt = [&](std::function<hipError_t(hipStream_t)> f) {
     if (!switch_fused) return;
     alt.enqueue = std::move(f);
-    alt.choose = [running]() { return running->load(std::memory_order_relaxed) >= 2; };
+    alt.choose = [conc]() { return conc->in_flight() >= 2; };
     altp = &alt;
   };
 
@@ -811,56 +821,79 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
                            stream, nullptr);
 }
 
-// One host thread per system, each running the single-system solve on its own
-// stream; the calling thread waits for all of them.  Error messages live in
-// thread-local storage, so each worker copies its own out.
+// A pool of host threads: worker w solves on streams[w] with workspace ws[w],
+// each taking the next unsolved system (index order) until none is left; the
+// calling thread waits for all of them.  Error messages live in thread-local
+// storage, so each worker copies its own out.
+constexpr int kMaxWorkers = 64;
 extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
                                             const double* omegas, double dt, double tol,
                                             int64_t max_steps, int32_t prec, double* const* rhos,
                                             int32_t* const* ranks, qpr_stats* stats,
-                                            const qpr_opts* opts, void* const* ws,
-                                            const size_t* wsb, const qpr_stream_t* streams) {
+                                            const qpr_opts* opts, int32_t nworkers,
+                                            void* const* ws, const size_t* wsb,
+                                            const qpr_stream_t* streams) {
   clear_error();
   if (count < 1) return fail(QPR_E_ARG, "count must be >= 1 (got %d)", count);
+  if (nworkers < 1 || nworkers > kMaxWorkers)
+    return fail(QPR_E_ARG, "nworkers must be in [1, %d] (got %d)", kMaxWorkers, nworkers);
   if (!probs || !omegas || !rhos || !ws || !wsb || !streams)
     return fail(QPR_E_ARG, "probs, omegas, rhos, ws, ws_bytes and streams must not be NULL");
-  for (int k = 0; k < count; ++k)
-    for (int j = 0; j < k; ++j)
-      if (streams[j] == streams[k])
-        return fail(QPR_E_ARG, "systems %d and %d share a stream", j, k);
+  for (int w = 0; w < nworkers; ++w)
+    for (int j = 0; j < w; ++j)
+      if (streams[j] == streams[w]) return fail(QPR_E_ARG, "workers %d and %d share a stream", j, w);
+  int nmax = 0;
+  for (int k = 0; k < count; ++k) {
+    if (!probs[k]) return fail(QPR_E_ARG, "probs[%d] is NULL", k);
+    nmax = std::max(nmax, probs[k]->n);
+  }
+  const size_t need = qpr_workspace_bytes(nmax, prec);
+  if (need == 0) return fail(QPR_E_ARG, "invalid problem size %d or precision %d", nmax, prec);
+  for (int w = 0; w < nworkers; ++w)
+    if (!ws[w] || wsb[w] < need)
+      return fail(QPR_E_WORKSPACE, "workspace %d has %zu bytes, the largest system needs %zu", w,
+                  ws[w] ? wsb[w] : (size_t)0, need);
+  nworkers = std::min(nworkers, count);
   int dev = 0;
   QPR_HIP(hipGetDevice(&dev));
   std::vector<qpr_status> status(count, QPR_OK);
   std::vector<std::string> msg(count);
   std::vector<qpr_stats> local(count);
-  std::atomic<int> running(count);
-  auto solve = [&](int k) {
-    if (hipSetDevice(dev) != hipSuccess) {
-      status[k] = QPR_E_HIP;
-      msg[k] = "hipSetDevice failed in the worker thread";
-      running.fetch_sub(1, std::memory_order_relaxed);
-      return;
+  Concurrency conc;
+  conc.remaining.store(count);
+  conc.workers = nworkers;
+  std::atomic<int> next(0);
+  auto work = [&](int w) {
+    const bool dev_ok = hipSetDevice(dev) == hipSuccess;
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= count) break;
+      if (!dev_ok) {
+        status[k] = QPR_E_HIP;
+        msg[k] = "hipSetDevice failed in the worker thread";
+      } else {
+        status[k] = steady_state_impl(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
+                                      ranks ? ranks[k] : nullptr, &local[k], opts, ws[w], wsb[w],
+                                      streams[w], &conc);
+        if (status[k] != QPR_OK) msg[k] = qpr_last_error();
+      }
+      conc.remaining.fetch_sub(1, std::memory_order_relaxed);
+      local[k].status = status[k];
     }
-    status[k] = steady_state_impl(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
-                                  ranks ? ranks[k] : nullptr, &local[k], opts, ws[k], wsb[k],
-                                  streams[k], &running);
-    running.fetch_sub(1, std::memory_order_relaxed);
-    local[k].status = status[k];
-    if (status[k] != QPR_OK) msg[k] = qpr_last_error();
   };
-  // a system whose worker cannot be started runs on the calling thread
-  std::vector<std::thread> workers;
+  // a worker that cannot be started runs on the calling thread
+  std::vector<std::thread> threads;
   std::vector<int> here;
-  workers.reserve(count);
-  for (int k = 0; k < count; ++k) {
+  threads.reserve(nworkers);
+  for (int w = 0; w < nworkers; ++w) {
     try {
-      workers.emplace_back(solve, k);
+      threads.emplace_back(work, w);
     } catch (const std::system_error&) {
-      here.push_back(k);
+      here.push_back(w);
     }
   }
-  for (int k : here) solve(k);
-  for (auto& t : workers) t.join();
+  for (int w : here) work(w);
+  for (auto& t : threads) t.join();
   if (stats)
     for (int k = 0; k < count; ++k) stats[k] = local[k];
   for (int k = 0; k < count; ++k)

@@ -121,7 +121,8 @@ def lib():
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                    C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_steady_state_many": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp,
-                                        C.POINTER(qpr_stats), C.POINTER(qpr_opts), vp, vp, vp]),
+                                        C.POINTER(qpr_stats), C.POINTER(qpr_opts), i32, vp, vp,
+                                        vp]),
         "qpr_rank": (i32, [i32, vp, vp, vp]),
         "qpr_hub_counts": (i32, [i32, vp, dbl, vp, vp]),
         "qpr_time_kernels": (i32, [P, dbl, i32, i32, i32, vp, C.POINTER(C.c_double), vp, sz, vp]),
@@ -388,14 +389,16 @@ def _pool_streams(k):
 def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0s=None,
                       want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1,
                       gemm_cfg=-1, allow_not_converged=False, product="auto", integrator="rk4",
-                      step_tol=1e-4, dt_max=0.0):
-    """Solve [(Problem, omega), ...] concurrently with qpr_steady_state_many, one
-    stream per system; each result is bitwise what steady_state returns."""
+                      step_tol=1e-4, dt_max=0.0, workers=8):
+    """Solve [(Problem, omega), ...] concurrently with qpr_steady_state_many: a
+    pool of min(workers, len(items)) host threads, each with its own stream and
+    workspace; each result is bitwise what steady_state returns."""
     torch = _torch()
     k = len(items)
-    streams = _pool_streams(k)
+    nw = max(1, min(int(workers), k))
+    streams = _pool_streams(nw)
     cur = torch.cuda.current_stream()
-    rhos, ranks, wss = [], [], []
+    rhos, ranks = [], []
     for i, (P, _) in enumerate(items):
         if rho0s is None or rho0s[i] is None:
             r = torch.zeros((2, P.n, P.n), dtype=torch.float64, device="cuda")
@@ -404,22 +407,24 @@ def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", r
             r = _planar_arg(rho0s[i], P.n).clone()
         rhos.append(r)
         ranks.append(torch.empty(P.n, dtype=torch.int32, device="cuda") if want_rank else None)
-        with torch.cuda.stream(streams[i]):
-            wss.append(workspace(P.n, prec))
-    for s in streams:        # the initial states are written on the current stream
-        s.wait_stream(cur)
+    nmax = max(P.n for P, _ in items)
+    wss = []
+    for s in streams:
+        with torch.cuda.stream(s):
+            wss.append(workspace(nmax, prec))
+        s.wait_stream(cur)   # the initial states are written on the current stream
     op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
                    dt_max)
     probs = (C.POINTER(qpr_problem) * k)(*[C.pointer(P.p) for P, _ in items])
     omegas = (C.c_double * k)(*[float(w) for _, w in items])
     rho_ptrs = (C.c_void_p * k)(*[r.data_ptr() for r in rhos])
     rank_ptrs = (C.c_void_p * k)(*[(r.data_ptr() if r is not None else None) for r in ranks])
-    ws_ptrs = (C.c_void_p * k)(*[w.ptr for w in wss])
-    ws_bytes = (C.c_size_t * k)(*[w.nbytes for w in wss])
-    handles = (C.c_void_p * k)(*[s.cuda_stream for s in streams])
+    ws_ptrs = (C.c_void_p * nw)(*[w.ptr for w in wss])
+    ws_bytes = (C.c_size_t * nw)(*[w.nbytes for w in wss])
+    handles = (C.c_void_p * nw)(*[s.cuda_stream for s in streams])
     stats = (qpr_stats * k)()
     status = lib().qpr_steady_state_many(k, probs, omegas, float(dt), float(tol), int(max_steps),
-                                         PREC[prec], rho_ptrs, rank_ptrs, stats, C.byref(op),
+                                         PREC[prec], rho_ptrs, rank_ptrs, stats, C.byref(op), nw,
                                          ws_ptrs, ws_bytes, handles)
     _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
     return [SolveResult(r, rk, st.as_dict(), st.status) for r, rk, st in zip(rhos, ranks, stats)]

@@ -123,12 +123,24 @@ def test_concurrent_solve_argument_errors_before_device_work():
     two = lambda t: (t * 2)()
     probs, omegas = two(C.c_void_p), (C.c_double * 2)(0.5, 0.5)
     rhos, ws, wsb = two(C.c_void_p), two(C.c_void_p), (C.c_size_t * 2)(1, 1)
-    args = (0.01, 1e-8, 10, 0, rhos, None, None, None, ws, wsb)
-    assert L.qpr_steady_state_many(0, probs, omegas, *args, two(C.c_void_p)) == qpr.QPR_E_ARG
-    assert L.qpr_steady_state_many(2, None, omegas, *args, two(C.c_void_p)) == qpr.QPR_E_ARG
+    head = (0.01, 1e-8, 10, 0, rhos, None, None, None)
+    many = L.qpr_steady_state_many
+    assert many(0, probs, omegas, *head, 2, ws, wsb, two(C.c_void_p)) == qpr.QPR_E_ARG
+    assert many(2, probs, omegas, *head, 0, ws, wsb, two(C.c_void_p)) == qpr.QPR_E_ARG
+    assert many(2, probs, omegas, *head, 65, ws, wsb, two(C.c_void_p)) == qpr.QPR_E_ARG
+    assert many(2, None, omegas, *head, 2, ws, wsb, two(C.c_void_p)) == qpr.QPR_E_ARG
     same = (C.c_void_p * 2)(4096, 4096)
-    assert L.qpr_steady_state_many(2, probs, omegas, *args, same) == qpr.QPR_E_ARG
+    assert many(2, probs, omegas, *head, 2, ws, wsb, same) == qpr.QPR_E_ARG
     assert "share a stream" in L.qpr_last_error().decode()
+    assert many(2, probs, omegas, *head, 2, ws, wsb, (C.c_void_p * 2)(4096, 8192)) == qpr.QPR_E_ARG
+    assert "probs[0] is NULL" in L.qpr_last_error().decode()
+    # a built-looking problem whose workspaces are too small
+    P = qpr.qpr_problem()
+    P.n, P.ld = 100, 128
+    ps = (C.c_void_p * 2)(C.addressof(P), C.addressof(P))
+    bad = (C.c_void_p * 2)(256, 512)
+    assert many(2, ps, omegas, *head, 2, bad, wsb, (C.c_void_p * 2)(4096, 8192)) == \
+        qpr.QPR_E_WORKSPACE
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

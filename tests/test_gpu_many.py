@@ -82,3 +82,17 @@ def test_many_reports_the_failing_system(Q):
         assert got.status == Q.QPR_E_NOT_CONVERGED
         ref = Q.steady_state(P, w, tol=1e-12, max_steps=50, allow_not_converged=True)
         assert torch.equal(got.rho, ref.rho)
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+def test_many_worker_pool(Q, workers):
+    """More systems than workers (mixed sizes): each worker takes the next
+    system on its own stream and workspace (sized for the largest system);
+    every result is bitwise the lone solve."""
+    gs = [inputs.family_graph(s) for s in (3, 4, 7, 10, 11)]
+    probs = [Q.Problem.from_graph(g) for g in gs]
+    items = [(P, w) for P in probs for w in (0.3, 0.8)][:9]
+    out = Q.steady_state_many(items, tol=1e-8, max_steps=400000, workers=workers)
+    assert len(out) == len(items)
+    for (P, w), got in zip(items, out):
+        _same(got, Q.steady_state(P, w, tol=1e-8, max_steps=400000))
