@@ -7,7 +7,8 @@ Bounds: a low-precision product row sums at most deg(a) terms of the FP32
 |X_lowp - X| <= c * 2^-24 * deg_max * max|rho|; the right-hand side inherits
 that times (1 - omega).  The steady state is judged by the FP64 residual, so
 the mixed solution must satisfy ||L(rho)||_F < tol re-measured by the oracle
-and lie within 1e-6 of the oracle's steady state (the benchmark spec's bound).
+and lie within 1e-6 of the oracle's steady state (the bound set for the mixed
+solves).
 """
 import numpy as np
 import pytest

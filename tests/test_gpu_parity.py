@@ -3,7 +3,7 @@
 Tolerances (FP64 throughout): the right-hand side and stage updates differ
 from the oracle only in summation order, |dL| <= ~deg * eps * max|rho|, so
 1e-12 absolute on trace-one states; step-locked trajectories stay within
-1e-10 (the benchmark spec's bound for plain FP64; observed ~1e-14); integer and
+1e-10 (the bound set for plain FP64; observed ~1e-14); integer and
 index outputs (CSR, degrees, ranking) are compared exactly.
 """
 import numpy as np
