@@ -254,6 +254,8 @@ def main():
                     help="also time qpr_batch_solve on this many family graphs x 5 omegas")
     ap.add_argument("--batch-rows", default="fp64,fp64_rkf45,fp64_rkf45_warm,fp32",
                     help="comma list of batched rows to time")
+    ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "concurrent"],
+                    help="how qpr_batch_solve runs the --batch-graphs systems")
     ap.add_argument("--precision-n", type=int, default=0,
                     help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
     ap.add_argument("--warm", default=WEIGHTS,
@@ -459,12 +461,14 @@ def main():
                 rho0s = W.warm_rho0_batch(items, params)
                 torch.cuda.synchronize()
                 t_inf = time.perf_counter() - t0i
-            rb = Q.batch_solve(items, tol=TOL, want_rank=True, rho0s=rho0s, **kw)
+            rb = Q.batch_solve(items, tol=TOL, want_rank=True, rho0s=rho0s,
+                               mode=args.batch_mode, **kw)
             st = [x["steps"] for x in rb.stats]
             secs = rb.seconds + t_inf
             extra[f"batch_{name}"] = {
                 "systems": len(items), "seconds": secs, "inference_seconds": t_inf,
                 "solves_per_s": len(items) / secs, "tuned_cfg": rb.tuned_cfg,
+                "mode": args.batch_mode,
                 "steps_min_mean_max": [min(st), float(np.mean(st)), max(st)],
                 "sum_n2": int(sum(Pk.n ** 2 for Pk, _ in items))}
             log(f"batch {name}: {len(items)} systems in {secs:.2f} s "

@@ -145,6 +145,9 @@ typedef struct {
   int32_t sparse_variant; /* sparse product kernel variant + 1, 0 = default [0];
                              variants as listed under qpr_time_kernels;
                              single-system calls only                    */
+  int32_t batch_mode;    /* qpr_batch_solve: qpr_batch_mode [QPR_BATCH_AUTO]  */
+  int32_t batch_workers; /* qpr_batch_solve, concurrent form: worker threads and
+                            streams, 0 = min(nsys, 8), at most 64 [0]        */
   double step_tol;    /* RKF45: local error tolerance per unit step [1e-4]    */
   double dt_max;      /* RKF45: step cap; 0 = from the spectral radius of H [0] */
 } qpr_opts;
@@ -172,6 +175,16 @@ typedef enum {
                              of the mixed solve gather the FP32 copy of the state the same way
                              (X rounded once to FP32, as the separate FP32 product) */
 } qpr_product;
+
+/* How qpr_batch_solve runs its systems. */
+typedef enum {
+  QPR_BATCH_AUTO = 0,       /* the concurrent form: faster than the persistent one on
+                               every batch measured (3 to 1,280 systems)               */
+  QPR_BATCH_PERSISTENT = 1, /* shared persistent launches over (system, tile) work lists,
+                               chunks replayed as one captured graph for all systems   */
+  QPR_BATCH_CONCURRENT = 2  /* single-system solves on a pool of worker streams, as
+                               qpr_steady_state_many                                   */
+} qpr_batch_mode;
 
 /* ------------------------------------------------------------------ build */
 
@@ -286,8 +299,10 @@ qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
                                  const size_t* ws_bytes, const qpr_stream_t* streams);
 
 /* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys)
- * with these options (NULL = defaults; opts->integrator = QPR_RKF45 adds each
- * system's Fehlberg stage planes).  0 for an invalid request. */
+ * with these options (NULL = defaults): the concurrent form takes one
+ * qpr_workspace_bytes(largest n, prec) per worker; the persistent form one
+ * workspace per system (opts->integrator = QPR_RKF45 adding each system's
+ * Fehlberg stage planes) plus its work lists.  0 for an invalid request. */
 size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
                                  const qpr_opts* opts);
 
@@ -296,24 +311,29 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  * steady state of Eq. (1) with RK4 (Supplementary Note 2) or, with
  * opts->integrator = QPR_RKF45 (FP64 only), the adaptive Fehlberg 4(5) of
  * qpr_steady_state with a step size and step control per system (dt = first
- * step, cap from the system's spectral bound unless opts->dt_max > 0; each
- * replayed chunk holds opts->chunk attempts) in shared launches:
- * every stage kernel covers all running systems through a device-side
- * (system, tile) work list; chunks of `opts->chunk` steps are replayed as one
- * captured HIP graph, and between replays the lists are shrunk to the systems
- * still running.  prec QPR_FP64 or QPR_FP32 (the FP32 product -- gathers of
- * the FP32 copy of delta, or FP32 MFMA tiles -- with the FP64 fold-and-judge
- * defect correction of qpr_steady_state, judged every chunk); the product
- * follows opts->product, decided on probs[0]'s density for the whole batch
- * (with AUTO the sparse stages, FP64 and FP32, run as fused epilogues: the
- * gathers in the tile kernel, one launch per stage).
- * The dense-product tile configuration is tuned on this batch's own work list
- * unless opts->gemm_cfg >= 0.
+ * step, cap from the system's spectral bound unless opts->dt_max > 0).
+ * prec QPR_FP64 or QPR_FP32 (the FP32 product with the FP64 fold-and-judge
+ * defect correction of qpr_steady_state).  Two forms (opts->batch_mode):
+ *  - concurrent (QPR_BATCH_AUTO, QPR_BATCH_CONCURRENT): single-system solves
+ *    on a pool of opts->batch_workers worker threads, each with a stream of
+ *    its own (created here, ordered after `stream`) and a workspace of its
+ *    own carved from ws, as qpr_steady_state_many; each system bitwise its
+ *    lone qpr_steady_state solve; opts->chunk steps per host check [64];
+ *  - persistent (QPR_BATCH_PERSISTENT): shared launches in which every stage
+ *    kernel covers all running systems through a device-side (system, tile)
+ *    work list; chunks of opts->chunk steps [32] (RKF45: attempts) are
+ *    replayed as one captured HIP graph, and between replays the lists are
+ *    shrunk to the systems still running; the product follows opts->product,
+ *    decided on probs[0]'s density for the whole batch (with AUTO the sparse
+ *    stages, FP64 and FP32, run as fused epilogues); the dense-product tile
+ *    configuration is tuned on this batch's own work list unless
+ *    opts->gemm_cfg >= 0.  Also bitwise the lone solves.
  *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are
  *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
  *           may be NULL or hold device int32[n_k] / NULL entries
  *   stats   HOST qpr_stats[nsys] or NULL (per-system status in stats[k].status)
- *   tuned_cfg  HOST int32 or NULL: the product configuration used (-1: none)
+ *   tuned_cfg  HOST int32 or NULL: the tuned product configuration of the
+ *           persistent form (-1: none, and always -1 in the concurrent form)
  * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP, and after a
  * full run QPR_E_NONFINITE / QPR_E_NOT_CONVERGED if any system failed.
  * Synchronises once per chunk.

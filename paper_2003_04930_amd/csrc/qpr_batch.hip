@@ -161,6 +161,19 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile, bool rkf)
   return L;
 }
 
+// The concurrent form (QPR_BATCH_AUTO, QPR_BATCH_CONCURRENT): its workers and
+// the arena of one single-system workspace per worker.
+bool batch_concurrent(const qpr_opts* o) { return !o || o->batch_mode != QPR_BATCH_PERSISTENT; }
+int batch_workers(int nsys, const qpr_opts* o) {
+  const int w = o && o->batch_workers > 0 ? o->batch_workers : 8;
+  return std::max(1, std::min(std::min(w, nsys), kMaxWorkers));
+}
+size_t worker_ws_stride(int nsys, const int* n, int prec) {
+  int nmax = 0;
+  for (int s = 0; s < nsys; ++s) nmax = std::max(nmax, n[s]);
+  return align_up(ws_bytes(nmax, prec));
+}
+
 }  // namespace
 }  // namespace qpr
 
@@ -173,6 +186,7 @@ extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int3
     if (n[s] < 2) return 0;
   const bool rkf = opts && opts->integrator == QPR_RKF45;
   if (rkf && prec != QPR_FP64) return 0;
+  if (batch_concurrent(opts)) return batch_workers(nsys, opts) * worker_ws_stride(nsys, n, prec);
   return batch_layout(nsys, n, prec, 32, rkf).total;
 }
 
@@ -192,13 +206,16 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
   if (!ws || ((uintptr_t)ws) % kAlign) return fail(QPR_E_ARG, "workspace must be 256-byte aligned");
   qpr_opts o{};
-  o.chunk = 32;
   o.use_graph = 1;
   o.renorm = 1;
   o.gemm_cfg = -1;
   o.product = QPR_PRODUCT_AUTO;
+  o.step_tol = 1e-4;
   if (opts) o = *opts;
-  if (o.chunk <= 0) o.chunk = 32;
+  if (o.batch_mode < QPR_BATCH_AUTO || o.batch_mode > QPR_BATCH_CONCURRENT)
+    return fail(QPR_E_ARG, "unknown batch_mode %d", o.batch_mode);
+  const bool concurrent = batch_concurrent(&o);
+  if (o.chunk <= 0) o.chunk = concurrent ? 64 : 32;
   const bool rkf = o.integrator == QPR_RKF45;
   if (rkf && prec != QPR_FP64) return fail(QPR_E_ARG, "the RKF45 integrator runs in FP64 only");
   if (rkf && !(o.step_tol > 0.0)) return fail(QPR_E_ARG, "step_tol must be positive");
@@ -217,10 +234,35 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       return fail(QPR_E_UNSTABLE, "system %d: dt=%g outside the RK4 stability bound", s, dt);
     ns[s] = P->n;
   }
+  hipStream_t s = (hipStream_t)stream;
+  if (concurrent) {
+    // one workspace and one stream per worker, the streams ordered after the
+    // caller's stream (where the initial states were written)
+    const int nw = batch_workers(nsys, &o);
+    const size_t stride = worker_ws_stride(nsys, ns.data(), prec);
+    if (ws_bytes_ < stride * nw)
+      return fail(QPR_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", ws_bytes_,
+                  stride * nw);
+    std::vector<void*> wsp(nw);
+    std::vector<size_t> wsb(nw, stride);
+    std::vector<HipStream> streams(nw);
+    std::vector<qpr_stream_t> hs(nw);
+    HipEvent ready;
+    QPR_HIP(hipEventCreateWithFlags(&ready.h, hipEventDisableTiming));
+    QPR_HIP(hipEventRecord(ready.h, s));
+    for (int w = 0; w < nw; ++w) {
+      wsp[w] = (char*)ws + stride * w;
+      QPR_HIP(hipStreamCreateWithFlags(&streams[w].h, hipStreamNonBlocking));
+      QPR_HIP(hipStreamWaitEvent(streams[w].h, ready.h, 0));
+      hs[w] = (qpr_stream_t)streams[w].h;
+    }
+    if (tuned_cfg) *tuned_cfg = -1;
+    return run_many(nsys, probs, omegas, dt, tol, max_steps, prec, rhos, ranks, stats, &o, nw,
+                    wsp.data(), wsb.data(), hs.data());
+  }
   const BatchLayout L = batch_layout(nsys, ns.data(), prec, 32, rkf);
   if (ws_bytes_ < L.total)
     return fail(QPR_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", ws_bytes_, L.total);
-  hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
   DevState* states = (DevState*)(base + L.states);
   BatchGemm* d_gemm = (BatchGemm*)(base + L.gemm_args);

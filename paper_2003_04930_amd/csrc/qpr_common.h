@@ -255,6 +255,15 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
 // largest step whose fourth-order update is stable for the spectrum bound of
 // the Liouvillian at omega (rho_h = spectral radius of H).
 EpiArgs rkf_stage_args(const Ws& w, int st, double omega, int xs);
+
+// Concurrent single-system solves: `nworkers` host threads, worker w on
+// streams[w] with workspace ws[w] (each large enough for the largest system),
+// taking systems in index order (qpr_steady_state_many).
+constexpr int kMaxWorkers = 64;
+qpr_status run_many(int count, const qpr_problem* const* probs, const double* omegas, double dt,
+                    double tol, int64_t max_steps, int prec, double* const* rhos,
+                    int32_t* const* ranks, qpr_stats* stats, const qpr_opts* opts, int nworkers,
+                    void* const* ws, const size_t* wsb, const qpr_stream_t* streams);
 double rkf_step_cap(double omega, double rho_h);
 
 // variant: index into the sparse-product variants (-1 = pv.spmm_variant);

@@ -825,15 +825,11 @@ extern "C" qpr_status qpr_steady_state(const qpr_problem* P, double omega, doubl
 // each taking the next unsolved system (index order) until none is left; the
 // calling thread waits for all of them.  Error messages live in thread-local
 // storage, so each worker copies its own out.
-constexpr int kMaxWorkers = 64;
-extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
-                                            const double* omegas, double dt, double tol,
-                                            int64_t max_steps, int32_t prec, double* const* rhos,
-                                            int32_t* const* ranks, qpr_stats* stats,
-                                            const qpr_opts* opts, int32_t nworkers,
-                                            void* const* ws, const size_t* wsb,
-                                            const qpr_stream_t* streams) {
-  clear_error();
+qpr_status qpr::run_many(int count, const qpr_problem* const* probs, const double* omegas,
+                         double dt, double tol, int64_t max_steps, int prec, double* const* rhos,
+                         int32_t* const* ranks, qpr_stats* stats, const qpr_opts* opts,
+                         int nworkers, void* const* ws, const size_t* wsb,
+                         const qpr_stream_t* streams) {
   if (count < 1) return fail(QPR_E_ARG, "count must be >= 1 (got %d)", count);
   if (nworkers < 1 || nworkers > kMaxWorkers)
     return fail(QPR_E_ARG, "nworkers must be in [1, %d] (got %d)", kMaxWorkers, nworkers);
@@ -899,6 +895,18 @@ extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* co
   for (int k = 0; k < count; ++k)
     if (status[k] != QPR_OK) return fail(status[k], "system %d: %s", k, msg[k].c_str());
   return QPR_OK;
+}
+
+extern "C" qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
+                                            const double* omegas, double dt, double tol,
+                                            int64_t max_steps, int32_t prec, double* const* rhos,
+                                            int32_t* const* ranks, qpr_stats* stats,
+                                            const qpr_opts* opts, int32_t nworkers,
+                                            void* const* ws, const size_t* wsb,
+                                            const qpr_stream_t* streams) {
+  clear_error();
+  return run_many(count, probs, omegas, dt, tol, max_steps, prec, rhos, ranks, stats, opts,
+                  nworkers, ws, wsb, streams);
 }
 
 extern "C" qpr_status qpr_hub_counts(int32_t n, const double* p, double c, int32_t* counts,

@@ -90,7 +90,8 @@ class qpr_mpnn_batch(C.Structure):
 class qpr_opts(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("use_graph", C.c_int32), ("fold_every", C.c_int32),
                 ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("product", C.c_int32),
-                ("integrator", C.c_int32), ("sparse_variant", C.c_int32), ("step_tol", C.c_double),
+                ("integrator", C.c_int32), ("sparse_variant", C.c_int32),
+                ("batch_mode", C.c_int32), ("batch_workers", C.c_int32), ("step_tol", C.c_double),
                 ("dt_max", C.c_double)]
 
 
@@ -308,11 +309,16 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
+BATCH_MODE = {"auto": 0, "persistent": 1, "concurrent": 2}
+
+
 def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto",
-              integrator="rk4", step_tol=1e-4, dt_max=0.0, sparse_variant=-1):
+              integrator="rk4", step_tol=1e-4, dt_max=0.0, sparse_variant=-1, batch_mode="auto",
+              batch_workers=0):
     return qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm),
                     int(gemm_cfg), PRODUCT[product], INTEGRATOR[integrator],
-                    int(sparse_variant) + 1, float(step_tol), float(dt_max))
+                    int(sparse_variant) + 1, BATCH_MODE[batch_mode], int(batch_workers),
+                    float(step_tol), float(dt_max))
 
 
 def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1,
@@ -575,14 +581,18 @@ class BatchResult:
 
 
 def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=None,
-                want_rank=True, chunk=32, use_graph=True, gemm_cfg=-1, product="auto",
-                allow_not_converged=False, integrator="rk4", step_tol=1e-4, dt_max=0.0):
-    """Solve [(Problem, omega), ...] together with qpr_batch_solve."""
+                want_rank=True, chunk=0, use_graph=True, gemm_cfg=-1, product="auto",
+                allow_not_converged=False, integrator="rk4", step_tol=1e-4, dt_max=0.0,
+                mode="auto", workers=0):
+    """Solve [(Problem, omega), ...] together with qpr_batch_solve (mode "auto" or
+    "concurrent": a pool of worker streams; "persistent": shared launches).
+    chunk 0 takes the library's default for the mode."""
     torch = _torch()
     import time as _time
     nsys = len(items)
     ns = (C.c_int32 * nsys)(*[P.n for P, _ in items])
-    op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product, integrator, step_tol, dt_max)
+    op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product, integrator, step_tol, dt_max,
+                   batch_mode=mode, batch_workers=workers)
     nbytes = lib().qpr_batch_workspace_bytes(nsys, ns, PREC[prec], C.byref(op))
     if nbytes == 0:
         raise QprError(QPR_E_ARG, "invalid batch request")

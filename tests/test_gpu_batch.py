@@ -6,6 +6,8 @@ reproduce each single solve bit for bit (same step count, same state);
 the FP32 batch is judged in FP64 and must meet the tolerance as re-measured
 by the oracle and stay within 1e-6 of the oracle's steady state.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -31,12 +33,13 @@ def small_family():
     return gs
 
 
+@pytest.mark.parametrize("mode", ["persistent", "auto"])
 @pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
-def test_fp64_batch_equals_single_solves(Q, product):
+def test_fp64_batch_equals_single_solves(Q, product, mode):
     gs = small_family()[:4]
     probs = [Q.Problem.from_graph(g) for g in gs]
     items = [(P, w) for P in probs for w in (0.3, 0.8)]
-    out = Q.batch_solve(items, tol=1e-9, product=product, chunk=16)
+    out = Q.batch_solve(items, tol=1e-9, product=product, chunk=16, mode=mode, workers=3)
     for k, (P, w) in enumerate(items):
         ref = Q.steady_state(P, w, 0.01, 1e-9, 400000, product=product)
         assert out.stats[k]["converged"] == 1
@@ -45,14 +48,17 @@ def test_fp64_batch_equals_single_solves(Q, product):
         assert torch.equal(out.ranks[k], ref.rank)
 
 
+@pytest.mark.parametrize("mode", ["persistent", "auto"])
 @pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
-def test_rkf45_batch_equals_single_solves(Q, product):
+def test_rkf45_batch_equals_single_solves(Q, product, mode):
     """Each system keeps its own Fehlberg step size and control; the batched
-    kernels reproduce the single adaptive solves bit for bit."""
+    kernels (and the concurrent form) reproduce the single adaptive solves bit
+    for bit."""
     gs = small_family()[:4]
     probs = [Q.Problem.from_graph(g) for g in gs]
     items = [(P, w) for P in probs for w in (0.2, 0.9)]
-    out = Q.batch_solve(items, tol=1e-9, product=product, chunk=8, integrator="rkf45")
+    out = Q.batch_solve(items, tol=1e-9, product=product, chunk=8, integrator="rkf45",
+                        mode=mode)
     for k, (P, w) in enumerate(items):
         ref = Q.steady_state(P, w, 0.01, 1e-9, 400000, product=product, integrator="rkf45")
         st = out.stats[k]
@@ -73,19 +79,21 @@ def test_rkf45_batch_rejects_low_precision(Q):
 def test_batch_graph_replay_equals_eager(Q):
     gs = small_family()[:3]
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.5,)]
-    a = Q.batch_solve(items, tol=1e-9, chunk=8, use_graph=True)
-    b = Q.batch_solve(items, tol=1e-9, chunk=8, use_graph=False)
+    a = Q.batch_solve(items, tol=1e-9, chunk=8, use_graph=True, mode="persistent")
+    b = Q.batch_solve(items, tol=1e-9, chunk=8, use_graph=False, mode="persistent")
     for x, y in zip(a.rhos, b.rhos):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("mode", ["persistent", "auto"])
 @pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
-def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product):
+def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, mode):
     gs = small_family()
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.1, 0.9)]
-    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32, product=product)
-    # the dense FP32 product is tuned on the batch; the sparse one has no tiles
-    assert (out.tuned_cfg >= 0) == (product == "dense")
+    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32, product=product, mode=mode)
+    # the persistent form tunes the dense FP32 product on the batch (the
+    # sparse one has no tiles); the concurrent form uses the solver's defaults
+    assert (out.tuned_cfg >= 0) == (product == "dense" and mode == "persistent")
     for k, ((P, w), g) in enumerate(zip(items, [g for g in gs for _ in (0.1, 0.9)])):
         st = out.stats[k]
         assert st["converged"] == 1 and st["folds"] >= 1
@@ -110,3 +118,32 @@ def test_batch_argument_errors(Q):
     assert e.value.status == Q.QPR_E_ARG
     out = Q.batch_solve([(P, 0.5)], tol=1e-14, max_steps=20, allow_not_converged=True)
     assert out.status == Q.QPR_E_NOT_CONVERGED and out.stats[0]["steps"] == 20
+
+
+def test_concurrent_batch_mixed_sizes_and_errors(Q):
+    """The concurrent form on more systems than workers, sizes 40..922, equals
+    the lone solves bitwise; its workspace query and errors."""
+    gs = [inputs.er_digraph(40, 0.1, seed=1), inputs.ba_digraph(922, 3, seed=0),
+          inputs.batch_graph(1), inputs.ba_digraph(75, 2, seed=2)]
+    probs = [Q.Problem.from_graph(g) for g in gs]
+    items = [(P, w) for P in probs for w in (0.4, 0.85)]
+    out = Q.batch_solve(items, tol=1e-8, workers=3)
+    for k, (P, w) in enumerate(items):
+        ref = Q.steady_state(P, w, 0.01, 1e-8, 400000)
+        assert out.stats[k]["steps"] == ref.stats["steps"]
+        assert torch.equal(out.rhos[k], ref.rho)
+    # two workers: two single-system workspaces of the largest system
+    L = Q.lib()
+    ns = (C.c_int32 * 3)(40, 922, 75)
+    conc = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(Q.make_opts(batch_workers=2)))
+    assert conc == 2 * L.qpr_workspace_bytes(922, 0)
+    pers = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(Q.make_opts(batch_mode="persistent")))
+    assert pers > 0 and pers != conc
+    # an unknown batch_mode is rejected before any device work
+    op = Q.make_opts()
+    op.batch_mode = 5
+    pa = (C.POINTER(Q.qpr_problem) * 1)(C.pointer(probs[0].p))
+    st = L.qpr_batch_solve(1, pa, (C.c_double * 1)(0.5), 0.01, 1e-8, 1000, 0,
+                           (C.c_void_p * 1)(out.rhos[0].data_ptr()), None, None, C.byref(op),
+                           None, C.c_void_p(256), 1 << 20, None)
+    assert st == Q.QPR_E_ARG and "batch_mode" in L.qpr_last_error().decode()
