@@ -195,8 +195,9 @@ def target_rows(Q, W, P, params, plain, plain_value, torch, np):
 
 
 def n4096_rows(Q, inputs, params, torch, np, args):
-    """Config-3 graph N = 4096 at omega = 0.8: plain FP64 RK4 against RKF45,
-    the accelerated solve and (unless --no-mixed) the FP32 mixed solve."""
+    """BA graph N = 4096 (m = 4) at omega = 0.8: plain FP64 RK4 against RKF45,
+    the accelerated solve and (unless --no-mixed) the FP32 mixed solve, cold
+    and from the warm start."""
     n, w = 4096, 0.8
     Pn = Q.Problem.from_graph(inputs.ba_digraph(n, 4, seed=0))
     torch.cuda.synchronize()
@@ -223,6 +224,11 @@ def n4096_rows(Q, inputs, params, torch, np, args):
                 Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), integrator="rkf45")
     if not args.no_mixed:
         runs["mixed_fp32"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, prec="fp32")
+        if params is not None:
+            from paper_2003_04930_amd import warmstart as W
+            # mixed precision from the learned warm start (inference included)
+            runs["mixed_fp32_warm"] = lambda: Q.steady_state(
+                Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), prec="fp32")
     for name, fn in runs.items():
         t0 = time.perf_counter()
         r = fn()
