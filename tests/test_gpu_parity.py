@@ -368,3 +368,39 @@ def test_steady_state_n922_properties(Q):
     Q.rk4_step(P, 0.8, 0.01, 8, x)
     want = O.rk4_ref(np.eye(922) / 922, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, 0.8), 0.01, 8)
     assert np.max(np.abs(Q.to_complex(x) - want)) < 1e-12
+
+
+@pytest.mark.parametrize("product", ["sparse", "fused", "dense"])
+def test_permutation_equivariance(Q, product):
+    """Relabelling the nodes permutes everything: L(P rho P^T) = P L(rho) P^T
+    for the relabelled graph, the steady state is the permuted one and the
+    ranking is the relabelled ranking (distinct populations here)."""
+    g = GRAPHS["ba130"]()
+    perm = np.random.default_rng(7).permutation(g.n)
+    gp = g.relabel(perm)
+    P1, P2 = Q.Problem.from_graph(g), Q.Problem.from_graph(gp)
+    rho = inputs.random_density(g.n, seed=31)
+    rho_p = np.empty_like(rho)
+    rho_p[np.ix_(perm, perm)] = rho                      # rho_p[perm[a], perm[b]] = rho[a, b]
+    l1 = Q.to_complex(Q.rhs(P1, 0.6, Q.planar(rho), product=product))
+    l2 = Q.to_complex(Q.rhs(P2, 0.6, Q.planar(rho_p), product=product))
+    assert np.max(np.abs(l2[np.ix_(perm, perm)] - l1)) < 1e-12
+    a = Q.steady_state(P1, 0.6, 0.01, 1e-10, 200000, product=product)
+    b = Q.steady_state(P2, 0.6, 0.01, 1e-10, 200000, product=product)
+    ra, rb = Q.to_complex(a.rho), Q.to_complex(b.rho)
+    assert np.max(np.abs(rb[np.ix_(perm, perm)] - ra)) < 1e-9
+    pa = np.diag(ra).real
+    if np.min(np.abs(np.diff(np.sort(pa)))) > 1e-8:       # no near-ties
+        assert list(b.rank.cpu().numpy()) == list(perm[a.rank.cpu().numpy()])
+
+
+@pytest.mark.parametrize("product,prec", [("sparse", "fp64"), ("fused", "fp64"),
+                                          ("dense", "fp64"), ("fused", "fp32")])
+def test_runs_are_bitwise_reproducible(Q, product, prec):
+    """Fixed-order reductions, no atomics on values: the same solve twice gives
+    the same bits (state, steps, residual)."""
+    P = Q.Problem.from_graph(GRAPHS["ba130"]())
+    a = Q.steady_state(P, 0.45, 0.01, 1e-9, 200000, prec=prec, product=product)
+    b = Q.steady_state(P, 0.45, 0.01, 1e-9, 200000, prec=prec, product=product)
+    assert torch.equal(a.rho, b.rho) and torch.equal(a.rank, b.rank)
+    assert a.stats["steps"] == b.stats["steps"] and a.stats["residual"] == b.stats["residual"]
