@@ -22,18 +22,6 @@ namespace {
 thread_local char g_err[512] = "";
 
 constexpr double kRk4Limit = 2.8;  // inside RK4's stability region on both axes
-
-struct Pinned {  // two pinned host copies of the device control block
-  DevState* buf = nullptr;
-  Pinned() {
-    if (hipHostMalloc((void**)&buf, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
-      buf = nullptr;
-  }
-};
-DevState* pinned_states() {
-  thread_local Pinned p;
-  return p.buf;
-}
 }  // namespace
 
 qpr_status fail(qpr_status s, const char* fmt, ...) {
@@ -559,14 +547,20 @@ struct AltChunk {
 qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chunk,
                       DevState* dev_st, bool use_graph, hipStream_t s, DevState* final_state,
                       long long* chunks_run, const AltChunk* alt = nullptr) {
-  DevState* hs = pinned_states();
-  if (!hs) return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
+  // two pinned host copies of the device control block, owned by this call
+  // (solves on several threads each have their own)
+  HostPinned pinned;
+  if (hipHostMalloc(&pinned.h, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
+  DevState* hs = (DevState*)pinned.h;
   hipGraphExec_t exec = nullptr, exec_alt = nullptr;
   hipGraph_t graph = nullptr, graph_alt = nullptr;
   hipStream_t cs = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   qpr_status rc = QPR_OK;
   auto cleanup = [&]() {
+    // nothing of this call may still be in flight (copies into `pinned`)
+    (void)hipStreamSynchronize(s);
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     if (exec_alt) hipGraphExecDestroy(exec_alt);
