@@ -143,6 +143,29 @@ def test_concurrent_solve_argument_errors_before_device_work():
         qpr.QPR_E_WORKSPACE
 
 
+def test_batch_workspace_query_and_mode_check():
+    """Host-side: the concurrent form needs one single-system workspace of
+    the largest system per worker; the persistent form more; an unknown
+    batch_mode is rejected before any device work."""
+    L = _lib()
+    ns = (C.c_int32 * 3)(40, 922, 75)
+    one = L.qpr_workspace_bytes(922, 0)
+    for workers, want in ((0, 3), (2, 2), (100, 3)):   # 0 = min(nsys, 8); capped at nsys
+        op = qpr.make_opts(batch_workers=workers)
+        assert L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(op)) == want * one
+    pers = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(qpr.make_opts(batch_mode="persistent")))
+    assert pers > 0 and pers != 3 * one
+    assert L.qpr_batch_workspace_bytes(3, ns, 2, None) == 0      # no BF16x3 batch
+    P = qpr.qpr_problem()
+    P.n, P.ld, P.h_off = 100, 128, C.c_void_p(256)
+    op = qpr.make_opts()
+    op.batch_mode = 5
+    st = L.qpr_batch_solve(1, (C.c_void_p * 1)(C.addressof(P)), (C.c_double * 1)(0.5), 0.01,
+                           1e-8, 10, 0, (C.c_void_p * 1)(256), None, None, C.byref(op), None,
+                           C.c_void_p(256), 1 << 20, None)
+    assert st == qpr.QPR_E_ARG and "batch_mode" in L.qpr_last_error().decode()
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(qpr, "_lib", None)
     monkeypatch.setattr(qpr, "LIB_PATH", str(tmp_path / "absent.so"))
