@@ -268,6 +268,56 @@ def test_golden_three_node_pagerank():
     assert list(O.rank_ref(want)) == [2, 0, 1]
 
 
+def test_golden_paper_hamiltonian_four_nodes():
+    """Eq. (S6) taken literally: -max(A_ij, A_ji) off the diagonal and the
+    negative out-degree on it, against a hand-written 4-node H."""
+    want = np.array([[float(v) for v in row] for row in _read_rows("h4_paper_hamiltonian.txt")])
+    src, dst = [0, 0, 1, 2, 3], [1, 2, 2, 1, 0]
+    A = O.adjacency(4, src, dst)
+    assert np.array_equal(O.hamiltonian(A, "paper"), want)
+    assert np.array_equal(O.problem_ref(4, src, dst, hdiag="paper").H, want)
+    # the two plausible mistakes the fixture is built to catch
+    indeg = A.sum(axis=1)
+    assert not np.array_equal(np.diag(want), -indeg)
+    assert not np.array_equal(np.diag(want), O.out_degree(A))
+
+
+def test_golden_two_node_paper_hamiltonian_closed_form():
+    """Steady state with the literal Eq. (S6) Hamiltonian (diagonal -outDeg):
+    its diagonal enters the coherences through (h_a - h_b) rho_ab."""
+    P = O.problem_ref(2, [0], [1], teleport="uniform", hdiag="paper")
+    assert np.array_equal(P.H, [[-1.0, -1.0], [-1.0, 0.0]])
+    for w, pn, pd, xn, xd, yn, yd in _read_rows("n2_paperH_uniform_edge01.txt"):
+        w = float(w)
+        rho, _, _ = O.steady_ref(np.eye(2) / 2, lambda r: P.rhs(r, w), 0.01, 1e-13, 400000)
+        assert abs(rho[0, 0].real - int(pn) / int(pd)) < 1e-12
+        assert abs(rho[0, 1].real - int(xn) / int(xd)) < 1e-12
+        assert abs(rho[0, 1].imag - int(yn) / int(yd)) < 1e-12
+
+
+@pytest.mark.parametrize("mistake", ["diag_sign", "diag_indegree", "diag_dropped"])
+def test_paper_hamiltonian_golden_catches_diagonal_mistakes(mistake):
+    """A flipped sign, in-degrees in place of out-degrees, or a dropped
+    diagonal in the Eq. (S6) Hamiltonian break the two-node closed form."""
+    P = O.problem_ref(2, [0], [1], teleport="uniform", hdiag="paper")
+    H = P.H.copy()
+    A = P.A
+    if mistake == "diag_sign":
+        H[np.diag_indices(2)] = O.out_degree(A)
+    elif mistake == "diag_indegree":
+        H[np.diag_indices(2)] = -A.sum(axis=1)
+    else:
+        H[np.diag_indices(2)] = 0.0
+    worst = 0.0
+    for w, pn, pd, xn, xd, yn, yd in _read_rows("n2_paperH_uniform_edge01.txt"):
+        w = float(w)
+        rho, _, _ = O.steady_ref(np.eye(2) / 2, lambda r: O.rhs_ref(r, H, P.G, P.d, w), 0.01,
+                                 1e-12, 400000)
+        worst = max(worst, abs(rho[0, 0].real - int(pn) / int(pd)),
+                    abs(rho[0, 1].real - int(xn) / int(xd)))
+    assert worst > 1e-3
+
+
 MUTANTS = {
     "commutator_sign": lambda rho, H, G, d, w:
         -1j * (1 - w) * (rho @ H - H @ rho) + w * (np.diag(G @ np.diag(rho)) - 0.5 * (d[:, None] + d[None, :]) * rho),
@@ -336,6 +386,48 @@ def test_fehlberg_order_conditions_fix_the_4104_reading():
     for s in range(6):
         assert np.allclose(O.FEHLBERG["a"][s], [float(x) for x in a[s]], rtol=0, atol=1e-16)
     assert np.allclose(O.FEHLBERG["b4"], [float(x) for x in b4], rtol=0, atol=1e-16)
+    assert np.allclose(O.FEHLBERG["b5"], [float(x) for x in b5], rtol=0, atol=1e-16)
+    assert np.allclose(O.FEHLBERG["c"], [float(x) for x in c], rtol=0, atol=1e-16)
+
+
+def test_fehlberg_weights_have_orders_four_and_five():
+    """All order conditions up to four for b4 and up to five for b5 (Butcher
+    trees, exact fractions on the oracle's own table read back as rationals),
+    so a wrong entry anywhere in a, b4 or b5 fails."""
+    F = Fraction
+    a = [[F(x).limit_denominator(100000) for x in row] for row in O.FEHLBERG["a"]]
+    c = [sum(row, F(0)) for row in a]
+    b4 = [F(x).limit_denominator(100000) for x in O.FEHLBERG["b4"]]
+    b5 = [F(x).limit_denominator(100000) for x in O.FEHLBERG["b5"]]
+    s = 6
+    A = [[a[i][j] if j < len(a[i]) else F(0) for j in range(s)] for i in range(s)]
+    Ac = [sum(A[i][j] * c[j] for j in range(s)) for i in range(s)]
+    Ac2 = [sum(A[i][j] * c[j] ** 2 for j in range(s)) for i in range(s)]
+    AAc = [sum(A[i][j] * Ac[j] for j in range(s)) for i in range(s)]
+    Ac3 = [sum(A[i][j] * c[j] ** 3 for j in range(s)) for i in range(s)]
+    AcAc = [sum(A[i][j] * c[j] * Ac[j] for j in range(s)) for i in range(s)]
+    AAc2 = [sum(A[i][j] * Ac2[j] for j in range(s)) for i in range(s)]
+    AAAc = [sum(A[i][j] * AAc[j] for j in range(s)) for i in range(s)]
+    dot = lambda b, v: sum(bi * vi for bi, vi in zip(b, v))
+    order4 = [(lambda b: dot(b, [1] * s), F(1)), (lambda b: dot(b, c), F(1, 2)),
+              (lambda b: dot(b, [x * x for x in c]), F(1, 3)), (lambda b: dot(b, Ac), F(1, 6)),
+              (lambda b: dot(b, [x ** 3 for x in c]), F(1, 4)),
+              (lambda b: dot(b, [ci * v for ci, v in zip(c, Ac)]), F(1, 8)),
+              (lambda b: dot(b, Ac2), F(1, 12)), (lambda b: dot(b, AAc), F(1, 24))]
+    order5 = [(lambda b: dot(b, [x ** 4 for x in c]), F(1, 5)),
+              (lambda b: dot(b, [ci * ci * v for ci, v in zip(c, Ac)]), F(1, 10)),
+              (lambda b: dot(b, [v * v for v in Ac]), F(1, 20)),
+              (lambda b: dot(b, [ci * v for ci, v in zip(c, Ac2)]), F(1, 15)),
+              (lambda b: dot(b, Ac3), F(1, 20)),
+              (lambda b: dot(b, [ci * v for ci, v in zip(c, AAc)]), F(1, 30)),
+              (lambda b: dot(b, AcAc), F(1, 40)), (lambda b: dot(b, AAc2), F(1, 60)),
+              (lambda b: dot(b, AAAc), F(1, 120))]
+    for cond, want in order4:
+        assert cond(b4) == want and cond(b5) == want
+    for cond, want in order5:
+        assert cond(b5) == want
+    # b4 is only fourth order: it misses the first fifth-order condition
+    assert order5[0][0](b4) != order5[0][1]
 
 
 def test_rkf45_tracks_matrix_exponential():
