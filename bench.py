@@ -78,30 +78,58 @@ def solve_sequential(Q, P):
     return [Q.steady_state(P, w, DT, TOL, 400000) for w in OMEGAS]
 
 
-def cpu_baseline(g, gpu_steps):
-    """Oracle RK4 steps on the host, extrapolated to the GPU's step counts."""
-    import numpy as np
-    import oracle as O
+def host_cpu():
+    """Host description for the CPU baseline: logical CPUs, model name, BLAS."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    blas, threads = "unknown", 1
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = max(int(d.get("num_threads", 1)) for d in info)
     except Exception:  # pragma: no cover
-        threads = 1
+        pass
+    return {"cpu_count": os.cpu_count(), "cpu_model": model, "blas": blas,
+            "blas_threads": threads,
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None}
+
+
+def cpu_baseline(g, gpu_steps, budget_s=20.0):
+    """The oracle's RK4 steps on the host's cores, the three omegas in turn,
+    until about `budget_s` seconds of CPU work (at most 120 steps per omega),
+    extrapolated to the GPU's mean step count per solve."""
+    import numpy as np
+    import oracle as O
+    host = host_cpu()
     R = O.problem_ref(g.n, g.src, g.dst)
-    rho = np.eye(g.n, dtype=np.complex128) / g.n
-    sample_steps = 30
+    rho0 = np.eye(g.n, dtype=np.complex128) / g.n
+    states = {w: rho0.copy() for w in OMEGAS}
+    done = 0
     t0 = time.perf_counter()
-    for w in OMEGAS:
-        O.rk4_ref(rho, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, w), DT, sample_steps // 3)
+    while time.perf_counter() - t0 < budget_s and done < 120 * len(OMEGAS):
+        w = OMEGAS[done % len(OMEGAS)]
+        states[w] = O.rk4_step_ref(states[w], lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, w), DT)
+        done += 1
     dt = time.perf_counter() - t0
-    per_step = dt / sample_steps
+    per_step = dt / done
     per_solve = per_step * float(np.mean(gpu_steps))
     return {
-        "value": 1.0 / per_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-        "seconds_per_solve": per_solve,
-        "sample": (f"{sample_steps} RK4 steps of the numpy/scipy FP64 oracle at N={g.n} "
-                   f"(10 per omega in {list(OMEGAS)}), {per_step * 1e3:.1f} ms/step, "
-                   f"extrapolated to the GPU's mean step count {float(np.mean(gpu_steps)):.0f}"),
+        "value": 1.0 / per_solve, "unit": "solves/s", "cores": int(host["blas_threads"]),
+        "kind": "oracle", "seconds_per_solve": per_solve, "host": host,
+        "sample": (f"{done} RK4 steps ({dt:.1f} s) of the numpy/scipy FP64 oracle at N={g.n}, "
+                   f"the omegas {list(OMEGAS)} in turn from I/N, {per_step * 1e3:.1f} ms/step, "
+                   f"extrapolated to the GPU's mean step count {float(np.mean(gpu_steps)):.0f} "
+                   f"per solve; cores = the BLAS threads (the sparse products run on one)"),
     }
 
 
@@ -213,8 +241,12 @@ def n4096_rows(Q, inputs, params, torch, np, args):
     # the stage kernel, no X round trip); the two-kernel stage is timed beside it
     row["stage_us"] = {"fused_epilogue": fused_ms * 1e3, "spmm": sp_ms * 1e3,
                        "epilogue": epi_ms * 1e3,
+                       "fused_GBs": 80.0 * n * n / (fused_ms * 1e-3) / 1e9,
+                       "fused_frac": 80.0 * n * n / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "fused_frac_unique_bytes": 50.0 * n * n / (fused_ms * 1e-3) / 1e9 /
+                       HBM_PEAK_GBS,
                        "spmm_GBs": 32.0 * n * n / (sp_ms * 1e-3) / 1e9,
-                       "epilogue_GBs": 58.0 * n * n / (epi_ms * 1e-3) / 1e9}
+                       "epilogue_GBs": 96.0 * n * n / (epi_ms * 1e-3) / 1e9}
     runs = {}
     if not args.no_rkf45:
         runs["fp64_rkf45"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, integrator="rkf45")
@@ -333,18 +365,23 @@ def main():
     fused_steps = sum(min(k, srt[-2]) for k in srt)
     alone_steps = srt[-1] - srt[-2]
     ld = P.ld
-    # algorithmic bytes per epilogue launch, unique data per element, the
-    # mean over the four RK4 stages (X 16 B read in full; Y_s, y_n, acc on the
-    # upper triangle 8 B each; acc written there 8 B; Y_s+1 written in full
-    # 16 B): stage 1 48, stages 2-3 64, stage 4 56 -> 58 B per element
-    epi_bytes = 58.0 * N * N
-    #   sparse product: each gathered row of Y read once from HBM (16 B/elem),
-    #   X written (16 B/elem); the nnz_H-fold re-reads hit the caches
-    sp_bytes = 32.0 * N * N
-    #   fused epilogue: the epilogue's bytes with the X read (16 B) and the
-    #   upper-triangle read of Y_s (8 B) replaced by Y_s gathered in full
-    #   (16 B): stage 1 40, stages 2-3 56, stage 4 48 -> 50 B per element
-    fused_bytes = 50.0 * N * N
+    # Algorithmic bytes per launch.  Per the hot-path scope (the measurement
+    # table of the fused passes) a fused RK4 stage moves ~80 B per element of
+    # the N x N state with tile-pair fusion (Y_s 16 read, y_n 16, accumulator
+    # 16 read + 16 written, Y_{s+1} 16 written) and ~128 B when X makes a round
+    # trip through HBM (X 16 written by the product and 16 read back, plus the
+    # product's 16 B read of Y); a sparse product reads Y once and writes X
+    # (32 B).  These are the figures `frac` uses.
+    # The kernels here touch less: y_n and the accumulator only on the upper
+    # triangle of tiles (Hermitian tile pairs), so the unique data per element
+    # is 58 B for the two-kernel epilogue (stage 1 48, stages 2-3 64, stage 4
+    # 56; X read in full) and 50 B for the fused epilogue (X gathered, Y_s read
+    # in full) -- reported beside them as "unique" bytes.
+    B_FUSED, B_TWO_KERNEL, B_SPMM = 80.0, 128.0 - 32.0, 32.0
+    U_FUSED, U_EPI = 50.0, 58.0
+    epi_bytes = B_TWO_KERNEL * N * N
+    sp_bytes = B_SPMM * N * N
+    fused_bytes = B_FUSED * N * N
     flops = 4.0 * N ** 3                       # dense product: two real N x N x N products
     gemm_tf = flops / (gemm_ms * 1e-3) / 1e12
     epi_gbs = epi_bytes / (epi_ms * 1e-3) / 1e9
@@ -353,20 +390,33 @@ def main():
     log(f"stage: spmm {sp_ms * 1e3:.1f} us ({sp_gbs:.0f} GB/s), epilogue {epi_ms * 1e3:.1f} us "
         f"({epi_gbs:.0f} GB/s), fused epilogue {fused_ms * 1e3:.1f} us ({fused_gbs:.0f} GB/s); "
         f"dense product {gemm_ms * 1e3:.1f} us ({gemm_tf:.1f} TF/s)")
+    # the whole timed region: every stage's algorithmic bytes over the wall time
+    timed_bytes = 4 * fused_steps * fused_bytes + 4 * alone_steps * (epi_bytes + sp_bytes)
+    agg_gbs = timed_bytes * args.steps / ((t1 - t0)) / 1e9
     if sparse:
         # the dominant kernel: the largest launch count x launch time
-        cands = [("k_epilogue_fused (sparse gathers + RHS + RK4 stage)", fused_gbs, fused_bytes,
-                  fused_ms, "fused", 4 * fused_steps),
-                 ("k_epilogue (fused RHS + RK4 stage)", epi_gbs, epi_bytes, epi_ms, "epilogue",
-                  4 * alone_steps),
+        cands = [("k_epilogue_fused<3> (sparse gathers + RHS + RK4 stage)", fused_gbs,
+                  fused_bytes, fused_ms, "fused", 4 * fused_steps, U_FUSED),
+                 ("k_epilogue<2> (fused RHS + RK4 stage)", epi_gbs, epi_bytes, epi_ms,
+                  "epilogue", 4 * alone_steps, U_EPI),
                  ("k_spmm (sparse commutator product)", sp_gbs, sp_bytes, sp_ms, "spmm",
-                  4 * alone_steps)]
+                  4 * alone_steps, B_SPMM)]
         dom = max(cands, key=lambda c: c[3] * c[5])
+        uniq = dom[6] * N * N
         roofline = {"bound": "hbm", "achieved": dom[1], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": dom[1] / HBM_PEAK_GBS, "traffic": measured_traffic(dom[4]),
-                    "kernel": dom[0], "bytes_per_launch": dom[2], "us_per_launch": dom[3] * 1e3,
+                    "kernel": dom[0], "bytes_per_launch": dom[2],
+                    "bytes_per_element": dom[2] / (N * N),
+                    "us_per_launch": dom[3] * 1e3,
+                    "launch_time": "the kernel alone, HIP events on its stream (qpr_time_kernels)",
                     "launches_in_timed_step": dom[5],
-                    "launch_time": "one kernel at a time, HIP events on its stream"}
+                    "unique_bytes_per_launch": uniq,
+                    "frac_unique_bytes": uniq / (dom[3] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "timed_region": {"stages_fused": 4 * fused_steps,
+                                     "stages_two_kernel": 4 * alone_steps,
+                                     "algorithmic_bytes_per_step": timed_bytes,
+                                     "aggregate_GBs": agg_gbs,
+                                     "aggregate_frac": agg_gbs / HBM_PEAK_GBS}}
     else:
         roofline = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": gemm_tf / FP64_PEAK_TFLOPS, "traffic": None,
@@ -382,11 +432,15 @@ def main():
                                "peak_TFs": FP64_PEAK_TFLOPS, "frac": gemm_tf / FP64_PEAK_TFLOPS,
                                "flops_per_launch": flops},
              "epilogue": {"us": epi_ms * 1e3, "achieved_GBs": epi_gbs,
-                          "frac": epi_gbs / HBM_PEAK_GBS, "bytes_per_launch": epi_bytes},
+                          "frac": epi_gbs / HBM_PEAK_GBS, "bytes_per_launch": epi_bytes,
+                          "frac_unique_bytes": U_EPI * N * N / (epi_ms * 1e-3) / 1e9 /
+                          HBM_PEAK_GBS},
              "spmm": {"us": sp_ms * 1e3, "achieved_GBs": sp_gbs,
                       "frac": sp_gbs / HBM_PEAK_GBS, "bytes_per_launch": sp_bytes},
              "fused_epilogue": {"us": fused_ms * 1e3, "achieved_GBs": fused_gbs,
-                                "frac": fused_gbs / HBM_PEAK_GBS, "bytes_per_launch": fused_bytes},
+                                "frac": fused_gbs / HBM_PEAK_GBS, "bytes_per_launch": fused_bytes,
+                                "frac_unique_bytes": U_FUSED * N * N / (fused_ms * 1e-3) / 1e9 /
+                                HBM_PEAK_GBS},
              "stages_in_timed_step": {"fused": 4 * fused_steps, "two_kernel": 4 * alone_steps},
              "nnz_h": int(P.p.nnz_h), "ld": ld}
 
@@ -415,6 +469,12 @@ def main():
 
     if not args.no_4096:
         extra["n4096"] = n4096_rows(Q, inputs, params, torch, np, args)
+        su = extra["n4096"]["stage_us"]
+        if sparse:
+            roofline["n4096_fused_stage"] = {
+                "us_per_launch": su["fused_epilogue"], "bytes_per_launch": 80.0 * 4096 ** 2,
+                "achieved": su["fused_GBs"], "frac": su["fused_frac"],
+                "frac_unique_bytes": su["fused_frac_unique_bytes"]}
 
     if not args.no_dense:
         t0d = time.perf_counter()

@@ -212,8 +212,11 @@ qpr_status qpr_build_google(int32_t n, int64_t n_edges, const int32_t* src,
                             int32_t hdiag, void* arena, size_t arena_bytes,
                             qpr_problem* out, qpr_stream_t stream);
 
-/* Bytes of workspace a solve of an n-node problem needs at precision prec. */
-size_t qpr_workspace_bytes(int32_t n, int32_t prec);
+/* Bytes of workspace a call on an n-node problem needs at precision prec with
+ * integrator `integrator` (qpr_integrator; QPR_RKF45 adds the Fehlberg stage
+ * planes and is FP64 only; qpr_rhs, qpr_rk4_step, qpr_time_kernels and
+ * qpr_autotune need the QPR_RK4 size).  0 for an invalid request. */
+size_t qpr_workspace_bytes(int32_t n, int32_t prec, int32_t integrator);
 
 /* ------------------------------------------------------------------ solve */
 
@@ -282,7 +285,7 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
  *   nworkers  1..64 (more than count is allowed; count are used)
  *   ws, ws_bytes, streams  HOST arrays [nworkers]: distinct streams, and
  *           non-overlapping 256-byte-aligned workspaces of at least
- *           qpr_workspace_bytes(largest n, prec) bytes each
+ *           qpr_workspace_bytes(largest n, prec, opts->integrator) bytes each
  * Returns QPR_OK when every system returns QPR_OK, else the status of the
  * lowest-numbered failing system, whose message qpr_last_error() gives
  * (prefixed "system k: "); stats[k].status holds each system's own status.
@@ -300,7 +303,7 @@ qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
 
 /* Bytes of workspace qpr_batch_solve needs for systems of sizes n[0..nsys)
  * with these options (NULL = defaults): the concurrent form takes one
- * qpr_workspace_bytes(largest n, prec) per worker; the persistent form one
+ * qpr_workspace_bytes(largest n, prec, integrator) per worker; the persistent form one
  * workspace per system (opts->integrator = QPR_RKF45 adding each system's
  * Fehlberg stage planes) plus its work lists.  0 for an invalid request. */
 size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
@@ -324,7 +327,7 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *    work list; chunks of opts->chunk steps [32] (RKF45: attempts) are
  *    replayed as one captured HIP graph, and between replays the lists are
  *    shrunk to the systems still running; the product follows opts->product,
- *    decided on probs[0]'s density for the whole batch (with AUTO the sparse
+ *    decided on the largest system's density for the whole batch (with AUTO the sparse
  *    stages, FP64 and FP32, run as fused epilogues); the dense-product tile
  *    configuration is tuned on this batch's own work list unless
  *    opts->gemm_cfg >= 0.  Also bitwise the lone solves.

@@ -168,10 +168,10 @@ int batch_workers(int nsys, const qpr_opts* o) {
   const int w = o && o->batch_workers > 0 ? o->batch_workers : 8;
   return std::max(1, std::min(std::min(w, nsys), kMaxWorkers));
 }
-size_t worker_ws_stride(int nsys, const int* n, int prec) {
+size_t worker_ws_stride(int nsys, const int* n, int prec, bool rkf) {
   int nmax = 0;
   for (int s = 0; s < nsys; ++s) nmax = std::max(nmax, n[s]);
-  return align_up(ws_bytes(nmax, prec));
+  return align_up(ws_bytes(nmax, prec, rkf));
 }
 
 }  // namespace
@@ -186,7 +186,8 @@ extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int3
     if (n[s] < 2) return 0;
   const bool rkf = opts && opts->integrator == QPR_RKF45;
   if (rkf && prec != QPR_FP64) return 0;
-  if (batch_concurrent(opts)) return batch_workers(nsys, opts) * worker_ws_stride(nsys, n, prec);
+  if (batch_concurrent(opts))
+    return batch_workers(nsys, opts) * worker_ws_stride(nsys, n, prec, rkf);
   return batch_layout(nsys, n, prec, 32, rkf).total;
 }
 
@@ -239,7 +240,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     // one workspace and one stream per worker, the streams ordered after the
     // caller's stream (where the initial states were written)
     const int nw = batch_workers(nsys, &o);
-    const size_t stride = worker_ws_stride(nsys, ns.data(), prec);
+    const size_t stride = worker_ws_stride(nsys, ns.data(), prec, rkf);
     if (ws_bytes_ < stride * nw)
       return fail(QPR_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", ws_bytes_,
                   stride * nw);
@@ -285,8 +286,15 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     if (o.product == QPR_PRODUCT_SPARSE || o.product == QPR_PRODUCT_FUSED) return true;
     return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
   };
-  const bool step_sparse = sparse_for(probs[0]);
-  const bool judge_sparse = sparse_for(probs[0]);
+  // one product form for all systems of the shared launches, decided on the
+  // largest system (the one whose stages cost the most); the small ones of a
+  // mixed-size batch may be denser than the threshold, which only changes
+  // their speed, never their result
+  int big = 0;
+  for (int k = 1; k < nsys; ++k)
+    if (probs[k]->n > probs[big]->n) big = k;
+  const bool step_sparse = sparse_for(probs[big]);
+  const bool judge_sparse = step_sparse;
   // FP64 sparse stages as fused epilogues (the gathers inside the tile
   // kernel, bitwise the same sums): the FP64 steps and the judge; the FP32
   // steps of the mixed solve keep their FP32 product.  AUTO fuses: over 160

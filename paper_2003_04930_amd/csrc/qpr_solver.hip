@@ -195,8 +195,10 @@ static qpr_status check_problem(const qpr_problem* P) {
   return QPR_OK;
 }
 
+// rkf: the solve may run the Fehlberg integrator, so the workspace must hold
+// its stage planes (RK4 solves and single right-hand sides do without them)
 static qpr_status check_common(const qpr_problem* P, double omega, int prec, void* ws,
-                               size_t ws_bytes_, Ws* w) {
+                               size_t ws_bytes_, Ws* w, bool rkf = false) {
   qpr_status st = check_problem(P);
   if (st != QPR_OK) return st;
   if (!(omega >= 0.0 && omega <= 1.0)) return fail(QPR_E_ARG, "omega must be in [0,1] (got %g)", omega);
@@ -204,9 +206,9 @@ static qpr_status check_common(const qpr_problem* P, double omega, int prec, voi
     return fail(QPR_E_ARG, "unknown precision %d", prec);
   if (!ws) return fail(QPR_E_ARG, "workspace must not be NULL");
   if (((uintptr_t)ws) % kAlign) return fail(QPR_E_ARG, "workspace must be 256-byte aligned");
-  if (!ws_carve(ws, ws_bytes_, P->n, prec, w))
+  if (!ws_carve(ws, ws_bytes_, P->n, prec, w, rkf))
     return fail(QPR_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes_,
-                ws_bytes(P->n, prec));
+                ws_bytes(P->n, prec, rkf));
   return QPR_OK;
 }
 
@@ -462,9 +464,11 @@ using namespace qpr;
 extern "C" const char* qpr_last_error(void) { return g_err; }
 extern "C" const char* qpr_version(void) { return "qpr 0.1 (gfx950)"; }
 
-extern "C" size_t qpr_workspace_bytes(int32_t n, int32_t prec) {
+extern "C" size_t qpr_workspace_bytes(int32_t n, int32_t prec, int32_t integrator) {
   if (n < 2 || (prec != QPR_FP64 && prec != QPR_FP32 && prec != QPR_BF16X3)) return 0;
-  return ws_bytes(n, prec);
+  if (integrator != QPR_RK4 && integrator != QPR_RKF45) return 0;
+  if (integrator == QPR_RKF45 && prec != QPR_FP64) return 0;
+  return ws_bytes(n, prec, integrator == QPR_RKF45);
 }
 
 static qpr_opts default_opts() {
@@ -544,15 +548,21 @@ struct AltChunk {
   std::function<hipError_t(hipStream_t)> enqueue;
   std::function<bool()> choose;
 };
+// `pinned` is two pinned host copies of the control block (a worker of a
+// concurrent solve passes the pair it owns for all its systems); NULL: this
+// call allocates its own (hipHostFree synchronises the device, so a worker
+// must not pay it per system).
 qpr_status run_chunks(const std::function<hipError_t(hipStream_t)>& enqueue_chunk,
                       DevState* dev_st, bool use_graph, hipStream_t s, DevState* final_state,
-                      long long* chunks_run, const AltChunk* alt = nullptr) {
-  // two pinned host copies of the device control block, owned by this call
-  // (solves on several threads each have their own)
-  HostPinned pinned;
-  if (hipHostMalloc(&pinned.h, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
-    return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
-  DevState* hs = (DevState*)pinned.h;
+                      long long* chunks_run, const AltChunk* alt = nullptr,
+                      DevState* pinned = nullptr) {
+  HostPinned own;
+  if (!pinned) {
+    if (hipHostMalloc(&own.h, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+      return fail(QPR_E_HIP, "hipHostMalloc of the control-block copies failed");
+    pinned = (DevState*)own.h;
+  }
+  DevState* hs = pinned;
   hipGraphExec_t exec = nullptr, exec_alt = nullptr;
   hipGraph_t graph = nullptr, graph_alt = nullptr;
   hipStream_t cs = nullptr;
@@ -644,16 +654,19 @@ struct Concurrency {
 static qpr_status steady_state_impl(const qpr_problem* P, double omega, double dt, double tol,
                                     int64_t max_steps, int32_t prec, double* rho, int32_t* rank,
                                     qpr_stats* stats, const qpr_opts* opts, void* ws, size_t wsb,
-                                    qpr_stream_t stream, const Concurrency* conc) {
+                                    qpr_stream_t stream, const Concurrency* conc,
+                                    DevState* pinned = nullptr) {
   const auto t0 = std::chrono::steady_clock::now();
   clear_error();
+  qpr_opts o = opts ? *opts : default_opts();
+  if (o.integrator != QPR_RK4 && o.integrator != QPR_RKF45)
+    return fail(QPR_E_ARG, "unknown integrator %d", o.integrator);
   Ws w;
-  qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
+  qpr_status st = check_common(P, omega, prec, ws, wsb, &w, o.integrator == QPR_RKF45);
   if (st != QPR_OK) return st;
   if (!rho) return fail(QPR_E_ARG, "rho must not be NULL");
   if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive (got %g)", tol);
   if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
-  qpr_opts o = opts ? *opts : default_opts();
   if (o.integrator == QPR_RKF45) {
     if (!(dt > 0.0)) return fail(QPR_E_ARG, "dt must be positive (got %g)", dt);
   } else if ((st = check_dt(P, omega, dt)) != QPR_OK) {
@@ -704,7 +717,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
       };
     };
     set_alt(chunk_of(QPR_PRODUCT_FUSED));
-    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp, pinned);
     if (st != QPR_OK) return st;
     S.steps = fs.accepted;
     S.rejected = fs.rejected;
@@ -726,7 +739,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
       };
     };
     set_alt(chunk_of(QPR_PRODUCT_FUSED));
-    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp, pinned);
     if (st != QPR_OK) return st;
     S.steps = fs.converged ? fs.conv_step : fs.step;
     S.rhs_evals = 4 * S.steps + 1;
@@ -775,7 +788,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
       };
     };
     set_alt(chunk_of(QPR_PRODUCT_FUSED));
-    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp);
+    st = run_chunks(chunk_of(product), w.st, graph, s, &fs, &chunks, altp, pinned);
     if (st != QPR_OK) return st;
     S.steps = fs.converged ? fs.conv_step : fs.step;
     S.folds = fs.folds;
@@ -837,7 +850,8 @@ qpr_status qpr::run_many(int count, const qpr_problem* const* probs, const doubl
     if (!probs[k]) return fail(QPR_E_ARG, "probs[%d] is NULL", k);
     nmax = std::max(nmax, probs[k]->n);
   }
-  const size_t need = qpr_workspace_bytes(nmax, prec);
+  const size_t need =
+      qpr_workspace_bytes(nmax, prec, opts ? opts->integrator : (int32_t)QPR_RK4);
   if (need == 0) return fail(QPR_E_ARG, "invalid problem size %d or precision %d", nmax, prec);
   for (int w = 0; w < nworkers; ++w)
     if (!ws[w] || wsb[w] < need)
@@ -854,17 +868,22 @@ qpr_status qpr::run_many(int count, const qpr_problem* const* probs, const doubl
   conc.workers = nworkers;
   std::atomic<int> next(0);
   auto work = [&](int w) {
-    const bool dev_ok = hipSetDevice(dev) == hipSuccess;
+    bool dev_ok = hipSetDevice(dev) == hipSuccess;
+    // this worker's pinned control-block copies, for all of its systems
+    HostPinned pin;
+    if (dev_ok && hipHostMalloc(&pin.h, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+      pin.h = nullptr;
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= count) break;
-      if (!dev_ok) {
+      if (!dev_ok || !pin.h) {
         status[k] = QPR_E_HIP;
-        msg[k] = "hipSetDevice failed in the worker thread";
+        msg[k] = dev_ok ? "hipHostMalloc of the control-block copies failed in the worker thread"
+                        : "hipSetDevice failed in the worker thread";
       } else {
         status[k] = steady_state_impl(probs[k], omegas[k], dt, tol, max_steps, prec, rhos[k],
                                       ranks ? ranks[k] : nullptr, &local[k], opts, ws[w], wsb[w],
-                                      streams[w], &conc);
+                                      streams[w], &conc, (DevState*)pin.h);
         if (status[k] != QPR_OK) msg[k] = qpr_last_error();
       }
       conc.remaining.fetch_sub(1, std::memory_order_relaxed);

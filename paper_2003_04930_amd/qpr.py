@@ -116,7 +116,7 @@ def lib():
     sig = {
         "qpr_problem_bytes": (sz, [i32, i64]),
         "qpr_build_google": (i32, [i32, i64, vp, vp, dbl, i32, i32, vp, sz, P, vp]),
-        "qpr_workspace_bytes": (sz, [i32, i32]),
+        "qpr_workspace_bytes": (sz, [i32, i32, i32]),
         "qpr_rhs": (i32, [P, dbl, vp, vp, i32, C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
@@ -240,31 +240,40 @@ class Problem:
         raise KeyError(name)
 
 
-class Workspace:
-    """Device workspace for one problem size and precision."""
+def workspace_bytes(n, prec="fp64", integrator="rk4"):
+    nbytes = lib().qpr_workspace_bytes(int(n), PREC[prec], INTEGRATOR[integrator])
+    if nbytes == 0:
+        raise QprError(QPR_E_ARG, f"invalid workspace request n={n} prec={prec} "
+                                  f"integrator={integrator}")
+    return nbytes
 
-    def __init__(self, n, prec="fp64", device="cuda"):
+
+class Workspace:
+    """Device workspace of at least `nbytes` bytes (256-byte aligned)."""
+
+    def __init__(self, nbytes, device="cuda"):
         torch = _torch()
-        nbytes = lib().qpr_workspace_bytes(int(n), PREC[prec])
-        if nbytes == 0:
-            raise QprError(QPR_E_ARG, f"invalid workspace request n={n} prec={prec}")
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         self.ptr = self.buf.data_ptr() + (-self.buf.data_ptr()) % 256
         self.nbytes = nbytes
-        self.n, self.prec = n, prec
 
 
 _ws_cache = {}
 
 
-def workspace(n, prec="fp64"):
-    """The cached workspace for (n, prec) on the current stream.  Calls on one
-    stream run in order and may share it; each other stream gets its own, so
-    solves on concurrent streams never share scratch memory."""
-    key = (int(n), prec, _stream().value)
+def workspace(n, prec="fp64", integrator="rk4"):
+    """The workspace of (prec, current stream), grown when a call needs more.
+    Calls on one stream run in order and share it (a larger buffer serves any
+    smaller problem); each other stream gets its own, so solves on concurrent
+    streams never share scratch memory.  A buffer that is replaced goes back
+    to torch's stream-ordered allocator, so work still queued on the stream
+    finishes with it before its memory is reused."""
+    need = workspace_bytes(n, prec, integrator)
+    key = (prec, _stream().value)
     ws = _ws_cache.get(key)
-    if ws is None:
-        ws = _ws_cache[key] = Workspace(n, prec)
+    if ws is None or ws.nbytes < need:
+        _ws_cache.pop(key, None)
+        ws = _ws_cache[key] = Workspace(need)
     return ws
 
 
@@ -371,7 +380,7 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
     st = qpr_stats()
     op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
                    dt_max)
-    ws = workspace(n, prec)
+    ws = workspace(n, prec, integrator)
     status = lib().qpr_steady_state(C.byref(P.p), float(omega), float(dt), float(tol),
                                     int(max_steps), PREC[prec], _ptr(rho), _ptr(rank),
                                     C.byref(st), C.byref(op), C.c_void_p(ws.ptr), ws.nbytes,
@@ -417,7 +426,7 @@ def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", r
     wss = []
     for s in streams:
         with torch.cuda.stream(s):
-            wss.append(workspace(nmax, prec))
+            wss.append(workspace(nmax, prec, integrator))
         s.wait_stream(cur)   # the initial states are written on the current stream
     op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
                    dt_max)

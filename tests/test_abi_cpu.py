@@ -66,11 +66,15 @@ def test_size_queries_and_version():
     assert L.qpr_problem_bytes(1, 0) == 0
     b922 = L.qpr_problem_bytes(922, 3031)
     assert b922 > 960 * 960 * (8 + 4 + 2)
-    assert L.qpr_workspace_bytes(1, 0) == 0
-    assert L.qpr_workspace_bytes(922, 7) == 0
-    w64 = L.qpr_workspace_bytes(922, 0)
-    assert w64 >= 22 * 960 * 960 * 8          # RK4 planes + Fehlberg K_1..K_5 and candidate
-    assert L.qpr_workspace_bytes(922, 2) >= 14 * 960 * 960 * 8
+    assert L.qpr_workspace_bytes(1, 0, 0) == 0
+    assert L.qpr_workspace_bytes(922, 7, 0) == 0
+    assert L.qpr_workspace_bytes(922, 0, 9) == 0        # unknown integrator
+    assert L.qpr_workspace_bytes(922, 1, 1) == 0        # RKF45 is FP64 only
+    w64 = L.qpr_workspace_bytes(922, 0, 0)
+    assert w64 >= 10 * 960 * 960 * 8          # y_n, two stage states, accumulator, X
+    rkf = L.qpr_workspace_bytes(922, 0, 1)
+    assert rkf >= w64 + 12 * 960 * 960 * 8    # + Fehlberg K_1..K_5 and the candidate
+    assert L.qpr_workspace_bytes(922, 2, 0) >= 14 * 960 * 960 * 8
     assert b"gfx950" in L.qpr_version()
 
 
@@ -149,10 +153,13 @@ def test_batch_workspace_query_and_mode_check():
     batch_mode is rejected before any device work."""
     L = _lib()
     ns = (C.c_int32 * 3)(40, 922, 75)
-    one = L.qpr_workspace_bytes(922, 0)
+    one = L.qpr_workspace_bytes(922, 0, 0)
     for workers, want in ((0, 3), (2, 2), (100, 3)):   # 0 = min(nsys, 8); capped at nsys
         op = qpr.make_opts(batch_workers=workers)
         assert L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(op)) == want * one
+    # RKF45 workers carry the Fehlberg planes, RK4 workers do not
+    op = qpr.make_opts(batch_workers=2, integrator="rkf45")
+    assert L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(op)) == 2 * L.qpr_workspace_bytes(922, 0, 1)
     pers = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(qpr.make_opts(batch_mode="persistent")))
     assert pers > 0 and pers != 3 * one
     assert L.qpr_batch_workspace_bytes(3, ns, 2, None) == 0      # no BF16x3 batch

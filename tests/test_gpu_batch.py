@@ -149,7 +149,7 @@ def test_concurrent_batch_mixed_sizes_and_errors(Q):
     L = Q.lib()
     ns = (C.c_int32 * 3)(40, 922, 75)
     conc = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(Q.make_opts(batch_workers=2)))
-    assert conc == 2 * L.qpr_workspace_bytes(922, 0)
+    assert conc == 2 * L.qpr_workspace_bytes(922, 0, 0)
     pers = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(Q.make_opts(batch_mode="persistent")))
     assert pers > 0 and pers != conc
     # an unknown batch_mode is rejected before any device work

@@ -351,22 +351,26 @@ def test_sparse_variant_out_of_range(Q):
         Q.rhs(P, 0.5, rho, product="sparse", sparse_variant=len(Q.SPARSE_VARIANTS))
 
 
-def test_steady_state_n922_properties(Q):
-    """Config-2 graph at omega = 0.8 to 1e-8: residual re-measured by the
-    oracle, trace, Hermiticity, positivity, and a step-locked prefix."""
+@pytest.mark.parametrize("omega", [0.2, 0.5, 0.8])
+def test_steady_state_n922_properties(Q, omega):
+    """Config-2 graph at each omega of the workload to 1e-8: residual
+    re-measured by the oracle, trace, Hermiticity, positivity, the ranking
+    rule, and a step-locked prefix against the oracle's RK4."""
     g = inputs.ba_digraph(922, 3, seed=0)
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
-    out = Q.steady_state(P, 0.8, 0.01, 1e-8, 200000)
+    out = Q.steady_state(P, omega, 0.01, 1e-8, 200000)
     rho = Q.to_complex(out.rho)
-    res = np.sqrt(np.sum(np.abs(O.rhs_ref(rho, R.H_sparse, R.G, R.d, 0.8)) ** 2))
+    res = np.sqrt(np.sum(np.abs(O.rhs_ref(rho, R.H_sparse, R.G, R.d, omega)) ** 2))
     assert res < 1e-8 * (1 + 1e-6)
     assert abs(np.trace(rho).real - 1) < 1e-11
     assert np.array_equal(rho, rho.conj().T)
     assert np.min(np.linalg.eigvalsh(rho)) > -1e-12
+    assert np.array_equal(out.rank.cpu().numpy(), O.rank_ref(np.diag(rho).real))
     x = Q.planar(np.eye(922) / 922)
-    Q.rk4_step(P, 0.8, 0.01, 8, x)
-    want = O.rk4_ref(np.eye(922) / 922, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, 0.8), 0.01, 8)
+    Q.rk4_step(P, omega, 0.01, 8, x)
+    want = O.rk4_ref(np.eye(922) / 922, lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, omega),
+                     0.01, 8)
     assert np.max(np.abs(Q.to_complex(x) - want)) < 1e-12
 
 
