@@ -245,6 +245,25 @@ qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt,
                         size_t ws_bytes, qpr_stream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * qpr_rk4_step with its workspace in a static device array the library
+ * holds on every GPU it runs on (about 84 MB each, for the life of the
+ * process) instead of a caller buffer.  Same arguments and results as
+ * qpr_rk4_step without ws/ws_bytes; prec must be QPR_FP64 and n <= 1024.
+ * Calls no allocating routine.  All calls on one GPU share that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race; calls
+ * on one stream run in order.  Nothing a previous call left in the array is
+ * read.
+ * Errors: those of qpr_rk4_step; QPR_E_ARG for n > 1024 or prec != QPR_FP64.
+ * Asynchronous.
+ */
+qpr_status qpr_rk4_step_noalloc(const qpr_problem* P, double omega, double dt,
+                                int32_t nsteps, double* rho, int32_t prec,
+                                double* diag_out, const qpr_opts* opts,
+                                qpr_stream_t stream);
+
+/*
  * Integrate from rho (in: rho0) until the first step n with
  * ||L(y_n)||_F < tol, FP64-judged, and return y_n in rho.  With prec != FP64
  * the solve is a defect correction: an FP64 anchor rho_a with FP64 residual

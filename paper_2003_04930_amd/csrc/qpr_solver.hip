@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <system_error>
 #include <thread>
@@ -1079,4 +1080,65 @@ extern "C" qpr_status qpr_load_tuning(const char* cache_path) {
   }
   fclose(f);
   return loaded > 0 ? QPR_OK : fail(QPR_E_ARG, "no entries in tuning cache %s", cache_path);
+}
+
+// ------------------------------------------------- no-allocation RK4 steps
+// qpr_rk4_step_noalloc: qpr_rk4_step with its workspace in a file-scope
+// device array instead of a caller buffer, for callers that cannot allocate
+// (graph capture, tight serving loops).  FP64 products only, n <= 1024: the
+// workspace of an FP64 RK4 call at n = 1024 (y_n, two stage states, the
+// accumulator and X, 2 x 1024^2 doubles each, plus the diagonals, partials
+// and control block) is 83,952,128 bytes.  Every GPU the library runs on
+// holds one such array for the life of the process; calls on one GPU share
+// it, so calls that overlap on one GPU race.  Everything a call reads is
+// written earlier in the same call (the padded state planes by the pad-in
+// kernel, the control block by the init kernel, the stage planes, the
+// accumulator and the partials by the stage kernels), so nothing left by a
+// previous call, of whatever size, is read.
+namespace {
+constexpr int kNoAllocMaxN = 1024;
+constexpr size_t kScratchBytes = 84 * 1024 * 1024;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's `scratch` (the host-side name is only
+// a stand-in), taken once per device with that device current.
+qpr_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  QPR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QPR_E_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    QPR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QPR_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QPR_OK;
+}
+}  // namespace
+
+extern "C" qpr_status qpr_rk4_step_noalloc(const qpr_problem* P, double omega, double dt,
+                                           int32_t nsteps, double* rho, int32_t prec,
+                                           double* diag_out, const qpr_opts* opts,
+                                           qpr_stream_t stream) {
+  clear_error();
+  qpr_status st = check_problem(P);
+  if (st != QPR_OK) return st;
+  if (P->n > kNoAllocMaxN)
+    return fail(QPR_E_ARG, "qpr_rk4_step_noalloc serves n <= %d (got n = %d)", kNoAllocMaxN,
+                P->n);
+  if (prec != QPR_FP64)
+    return fail(QPR_E_ARG, "qpr_rk4_step_noalloc runs FP64 products only (got prec %d)", prec);
+  const size_t need = ws_bytes(P->n, prec, false);
+  if (need > kScratchBytes)
+    return fail(QPR_E_WORKSPACE, "static scratch of %zu bytes, n = %d needs %zu", kScratchBytes,
+                P->n, need);
+  void* ws = nullptr;
+  if ((st = scratch_for_current_device(&ws)) != QPR_OK) return st;
+  return qpr_rk4_step(P, omega, dt, nsteps, rho, prec, diag_out, opts, ws, kScratchBytes, stream);
 }

@@ -38,7 +38,7 @@ EXPORTS = (
     "qpr_mpnn_param_count", "qpr_mpnn_workspace_bytes", "qpr_mpnn_features",
     "qpr_mpnn_forward", "qpr_mpnn_backward", "qpr_mpnn_adam", "qpr_autotune",
     "qpr_load_tuning", "qpr_batch_workspace_bytes", "qpr_batch_solve", "qpr_hub_counts",
-    "qpr_sparse_variants", "qpr_sparse_variant_name",
+    "qpr_sparse_variants", "qpr_sparse_variant_name", "qpr_rk4_step_noalloc",
 )
 
 
@@ -119,6 +119,7 @@ def lib():
         "qpr_workspace_bytes": (sz, [i32, i32, i32]),
         "qpr_rhs": (i32, [P, dbl, vp, vp, i32, C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_rk4_step": (i32, [P, dbl, dbl, i32, vp, i32, vp, C.POINTER(qpr_opts), vp, sz, vp]),
+        "qpr_rk4_step_noalloc": (i32, [P, dbl, dbl, i32, vp, i32, vp, C.POINTER(qpr_opts), vp]),
         "qpr_steady_state": (i32, [P, dbl, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
                                    C.POINTER(qpr_opts), vp, sz, vp]),
         "qpr_steady_state_many": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp,
@@ -355,6 +356,18 @@ def rk4_step(P: Problem, omega, dt, nsteps, rho, prec="fp64", diag=False, produc
                               PREC[prec], _ptr(d), C.byref(op), C.c_void_p(ws.ptr), ws.nbytes,
                               _stream()))
     return d
+
+
+def rk4_step_noalloc(P: Problem, omega, dt, nsteps, rho, diag=None, product="auto"):
+    """qpr_rk4_step_noalloc: nsteps FP64 RK4 steps in place, the workspace in the
+    library's static device array (n <= 1024).  `diag`, if given, is a device
+    float64 tensor of 4 that receives [res^2, trace, herm, nonfinite]."""
+    rho = _planar_arg(rho, P.n)
+    op = make_opts(product=product)
+    _check(lib().qpr_rk4_step_noalloc(C.byref(P.p), float(omega), float(dt), int(nsteps),
+                                      _ptr(rho), PREC["fp64"], _ptr(diag), C.byref(op),
+                                      _stream()))
+    return diag
 
 
 @dataclass
