@@ -150,6 +150,15 @@ typedef struct {
                             streams, 0 = min(nsys, 8), at most 64 [0]        */
   double step_tol;    /* RKF45: local error tolerance per unit step [1e-4]    */
   double dt_max;      /* RKF45: step cap; 0 = from the spectral radius of H [0] */
+  int32_t delta_state; /* mixed precision (QPR_FP32): storage of the defect delta,
+                          its RK4 stage states, accumulator and the copy of r_a
+                          the steps add: 1 FP64 (the stage writes an FP32 copy for
+                          the product), 2 FP32 (every state plane of the steps
+                          single precision, arithmetic FP64; needs the sparse
+                          product), 0 = FP32 with QPR_PRODUCT_AUTO where the
+                          product is sparse, else FP64 [0].  qpr_steady_state,
+                          qpr_steady_state_many and the concurrent batch form  */
+  int32_t reserved;
 } qpr_opts;
 
 /* Time integrator of qpr_steady_state. */

@@ -118,6 +118,12 @@ struct Ws {
   double *an_r = nullptr, *an_i = nullptr;   // mixed: FP64 anchor rho_a
   float *xf_r = nullptr, *xf_i = nullptr;    // FP32 products (mixed modes)
   float *lo_r = nullptr, *lo_i = nullptr;    // FP32 operand copy (QPR_FP32)
+  // QPR_FP32 with the defect held in FP32 (each pair of FP32 planes lives in
+  // the bytes of an FP64 plane pair that this mode leaves unused): delta_n,
+  // the two stage states, the accumulator, and the FP32 copy of r_a
+  float *dn_r = nullptr, *dn_i = nullptr, *d1_r = nullptr, *d1_i = nullptr;
+  float *d2_r = nullptr, *d2_i = nullptr, *dac_r = nullptr, *dac_i = nullptr;
+  float *ra32_r = nullptr, *ra32_i = nullptr;
   uint16_t* sl = nullptr;                    // bf16 slices: [plane][slice][ld*ld]
   double *p_n = nullptr, *p_1 = nullptr, *p_2 = nullptr, *p_a = nullptr; // diagonals (n)
   double *k_r[5] = {}, *k_i[5] = {};         // Fehlberg stage derivatives (FP64 only)
@@ -170,7 +176,9 @@ enum XSource {
   XS_DENSE32 = 1,   // FP32 X written by a low-precision dense product
   XS_SPARSE64 = 2,  // FP64 X written by the sparse product (k_spmm)
   XS_FUSED64 = 3,   // FP64 X gathered inside the epilogue tile (no product launch)
-  XS_FUSED32 = 4    // the same from the FP32 copy of Y_s (xfr/xfi), X rounded to FP32
+  XS_FUSED32 = 4,   // the same from the FP32 copy of Y_s (xfr/xfi), X rounded to FP32
+  XS_FUSED32S = 5   // FP32 state: every state plane of the stage is FP32 (the defect of
+                    // the mixed solve); gathers and X as XS_FUSED32, xfr/xfi = Y_s
 };
 
 struct EpiArgs {
@@ -220,6 +228,9 @@ hipError_t launch_hubs(int n, const double* p, double c, int* out, hipStream_t s
 hipError_t launch_axpy_planes(double* yr, double* yi, const double* xr,
                               const double* xi, double a, int n, int ld,
                               double* p, const DevState* st, hipStream_t s);
+hipError_t launch_axpy_planes_f32(double* yr, double* yi, const float* xr, const float* xi,
+                                  double a, int n, int ld, double* p, const DevState* st,
+                                  hipStream_t s);
 hipError_t launch_trace(const double* p, int n, DevState* st, hipStream_t s);
 hipError_t launch_rkf_commit(double* yr, double* yi, double* p, const double* cr,
                              const double* ci, const double* pc, int n, int ld,

@@ -163,6 +163,17 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
     if (prec == QPR_FP32) {
       w->lo_r = (float*)(b + L.lo);
       w->lo_i = w->lo_r + pl;
+      // the FP32 defect planes, in FP64 regions the FP32-state solve leaves unused
+      w->dn_r = (float*)(b + L.yn);
+      w->dn_i = w->dn_r + pl;
+      w->d1_r = (float*)(b + L.y1);
+      w->d1_i = w->d1_r + pl;
+      w->d2_r = (float*)(b + L.y2);
+      w->d2_i = w->d2_r + pl;
+      w->dac_r = (float*)(b + L.acc);
+      w->dac_i = w->dac_r + pl;
+      w->ra32_r = (float*)(b + L.x);
+      w->ra32_i = w->ra32_r + pl;
     }
     if (prec == QPR_BF16X3) w->sl = (uint16_t*)(b + L.sl);
   }
@@ -313,7 +324,8 @@ static hipError_t enqueue_step(const qpr_problem* P, const Ws& w, const ProbView
 // L(Y) for Y in (inr, ini, pin) into (outr, outi); FP64 product unless xk says otherwise.
 static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView& pv, double omega,
                               double* inr, double* ini, double* pin, double* outr, double* outi,
-                              int xk, int cfg, int product, int check, hipStream_t s) {
+                              int xk, int cfg, int product, int check, hipStream_t s,
+                              float* lor = nullptr, float* loi = nullptr) {
   const bool sparse = use_sparse(P, product, xk);
   const int xs = x_source(P, product, xk);
   if (xk != OP_F64) {
@@ -341,8 +353,60 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
     a.xfr = w.lo_r;
     a.xfi = w.lo_i;
   }
+  a.lor = lor;  // also store the result rounded to FP32 (the FP32-state defect's r_a)
+  a.loi = loi;
   a.check = check;
   return launch_epilogue(pv, a, w, s);
+}
+
+// Classical RK4 stage k of the defect step with the defect held in FP32
+// (XS_FUSED32S): d delta/dt = r_a + L(delta), every state plane FP32 (delta_n,
+// the ping-pong stage states, the accumulator, the FP32 copy of r_a); the
+// stage gathers X from its FP32 input; arithmetic in FP64.  Same rotation as
+// rk4_stage_args: delta_n -> D_1 -> D_2 -> D_1 -> delta_n.
+static EpiArgs rk4_stage_args_f32s(const Ws& w, int k, double omega, double dt, int check,
+                                   int gate) {
+  float* in_r[4] = {w.dn_r, w.d1_r, w.d2_r, w.d1_r};
+  float* in_i[4] = {w.dn_i, w.d1_i, w.d2_i, w.d1_i};
+  float* out_r[4] = {w.d1_r, w.d2_r, w.d1_r, w.dn_r};
+  float* out_i[4] = {w.d1_i, w.d2_i, w.d1_i, w.dn_i};
+  double* pin[4] = {w.p_n, w.p_1, w.p_2, w.p_1};
+  double* pout[4] = {w.p_1, w.p_2, w.p_1, w.p_n};
+  const double cdt[4] = {0.5 * dt, 0.5 * dt, dt, dt / 6.0};
+  EpiArgs a{};
+  a.xfr = in_r[k];  // the gathers read the FP32 stage input itself
+  a.xfi = in_i[k];
+  a.ysr = (const double*)in_r[k];  // FP32 planes (XS_FUSED32S reads them as such)
+  a.ysi = (const double*)in_i[k];
+  a.ps = pin[k];
+  a.ynr = (const double*)w.dn_r;
+  a.yni = (const double*)w.dn_i;
+  a.accr = (double*)w.dac_r;
+  a.acci = (double*)w.dac_i;
+  a.outr = (double*)out_r[k];
+  a.outi = (double*)out_i[k];
+  a.pout = pout[k];
+  a.rar = (const double*)w.ra32_r;
+  a.rai = (const double*)w.ra32_i;
+  a.omega = omega;
+  a.cdt = cdt[k];
+  a.mode = EPI_S1 + k;
+  a.xkind = XS_FUSED32S;
+  a.check = k == 0 ? check : CHK_NONE;
+  a.gate = gate;
+  return a;
+}
+
+// One RK4 step of the FP32-state defect: four fused launches (gated by the
+// hold of the defect correction, so stage 1 keeps its own finishing launch).
+static hipError_t enqueue_step_f32s(const ProbView& pv, const Ws& w, double omega, double dt,
+                                    int check, hipStream_t s) {
+  const int gate = check == CHK_DELTA ? 1 : 0;
+  for (int k = 0; k < 4; ++k) {
+    hipError_t e = launch_epilogue(pv, rk4_stage_args_f32s(w, k, omega, dt, check, gate), w, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Fehlberg 4(5) tableau (Supplementary Note 2, Eq. (S10)-(S12)), the two
@@ -483,6 +547,7 @@ static qpr_opts default_opts() {
   o.integrator = QPR_RK4;
   o.step_tol = 1e-4;
   o.dt_max = 0.0;
+  o.delta_state = 0;
   return o;
 }
 
@@ -757,6 +822,56 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
     out_i = w.an_i;
     out_p = w.p_a;
     const size_t plane = (size_t)ld * ld;
+    // Where the defect is stored: FP32 (every state plane of the steps single
+    // precision, half the bytes per stage) by default wherever the FP32 steps
+    // take the fused sparse stage, else FP64 (the stage writes an FP32 copy
+    // of its output for the next product).
+    const bool sparse32 = xk == OP_F32 && use_sparse(P, product, OP_F32);
+    if (o.delta_state < 0 || o.delta_state > 2)
+      return fail(QPR_E_ARG, "delta_state must be 0, 1 or 2 (got %d)", o.delta_state);
+    if (o.delta_state == 2 && !sparse32)
+      return fail(QPR_E_ARG, "an FP32 defect needs prec QPR_FP32 with the sparse product");
+    const bool state32 =
+        o.delta_state == 2 || (o.delta_state == 0 && sparse32 && product == QPR_PRODUCT_AUTO);
+    if (state32) {
+      auto reset32 = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = launch_fill(w.dn_r, 2 * plane * 4, q);
+        if (e == hipSuccess) e = launch_fill(w.p_n, (size_t)ld * 8, q);
+        return e;
+      };
+      // fold the FP32 defect into the FP64 anchor, renormalise, judge in FP64
+      // (fused sparse stage) and keep r_a in FP64 and as the FP32 copy the
+      // steps add
+      auto fold_judge32 = [&](hipStream_t q, bool first) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (!first)
+          e = launch_axpy_planes_f32(w.an_r, w.an_i, w.dn_r, w.dn_i, 1.0, n, ld, w.p_a, w.st, q);
+        if (e == hipSuccess && o.renorm) e = launch_trace(w.p_a, n, w.st, q);
+        if (e == hipSuccess && o.renorm) e = launch_scale_planes(w.an_r, w.an_i, w.p_a, n, ld, w.st, q);
+        if (e == hipSuccess)
+          e = enqueue_rhs(P, w, pv, omega, w.an_r, w.an_i, w.p_a, w.ra_r, w.ra_i, OP_F64,
+                          o.gemm_cfg, QPR_PRODUCT_FUSED, CHK_JUDGE, q, w.ra32_r, w.ra32_i);
+        if (e == hipSuccess) e = reset32(q);
+        return e;
+      };
+      QPR_HIP(launch_state_init(w.st, tol, max_steps, CHK_DELTA, s));
+      QPR_HIP(launch_pad_in(rho, n, ld, w.an_r, w.an_i, w.p_a, s));
+      QPR_HIP(fold_judge32(s, true));
+      auto chunk32 = [&](hipStream_t q) -> hipError_t {
+        for (int k = 0; k < o.fold_every; ++k) {
+          hipError_t e = enqueue_step_f32s(pv, w, omega, dt, CHK_DELTA, q);
+          if (e != hipSuccess) return e;
+        }
+        return fold_judge32(q, false);
+      };
+      st = run_chunks(chunk32, w.st, graph, s, &fs, &chunks, nullptr, pinned);
+      if (st != QPR_OK) return st;
+      S.steps = fs.converged ? fs.conv_step : fs.step;
+      S.folds = fs.folds;
+      S.rhs_evals_fp64 = fs.folds;
+      S.rhs_evals = 4 * S.steps + fs.folds;
+      S.residual = std::sqrt(fs.judge2);
+    } else {
     auto reset_delta = [&](hipStream_t q) -> hipError_t {
       hipError_t e = launch_fill(w.yn_r, 2 * plane * 8, q);
       if (e == hipSuccess) e = launch_fill(w.p_n, (size_t)ld * 8, q);
@@ -796,6 +911,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
     S.rhs_evals_fp64 = fs.folds;
     S.rhs_evals = 4 * S.steps + fs.folds;
     S.residual = std::sqrt(fs.judge2);
+    }
   }
   S.converged = fs.converged;
   if (fs.nonfinite) result = fail(QPR_E_NONFINITE, "non-finite value in the state or L(rho)");

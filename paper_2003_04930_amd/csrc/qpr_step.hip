@@ -20,6 +20,7 @@
 // step) on the device.
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 
 #include "qpr_common.h"
 #include "qpr_device.h"
@@ -229,13 +230,30 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const T* __rest
 // are read there only (the accumulator is only ever stored there), while the
 // next stage state -- which the product reads in full -- is written to (I, J)
 // and, conjugated, to (J, I).
+// XS_FUSED32S: every state plane (Y_s, y_n, the accumulator, the anchor
+// residual and the output) is FP32 (the defect of the mixed solve held in
+// single precision); the arithmetic stays FP64, each stored value is the
+// FP32 rounding of the FP64 result, and the mirrored tile stores the
+// conjugate of exactly that value (so the stored state stays bitwise
+// Hermitian).
 template <int XS>
 __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs& a,
                                               DevState* __restrict__ st,
                                               double* __restrict__ partials, int tile) {
   __shared__ double Tr[TE][TE + 1], Ti[TE][TE + 1];
   __shared__ double Or[TE][TE + 1], Oi[TE][TE + 1];
-  constexpr bool FUSED = XS == XS_FUSED64 || XS == XS_FUSED32;
+  constexpr bool FUSED = XS == XS_FUSED64 || XS == XS_FUSED32 || XS == XS_FUSED32S;
+  using ST = typename std::conditional<XS == XS_FUSED32S, float, double>::type;
+  const ST* __restrict__ s_ysr = reinterpret_cast<const ST*>(a.ysr);
+  const ST* __restrict__ s_ysi = reinterpret_cast<const ST*>(a.ysi);
+  const ST* __restrict__ s_ynr = reinterpret_cast<const ST*>(a.ynr);
+  const ST* __restrict__ s_yni = reinterpret_cast<const ST*>(a.yni);
+  const ST* __restrict__ s_rar = reinterpret_cast<const ST*>(a.rar);
+  const ST* __restrict__ s_rai = reinterpret_cast<const ST*>(a.rai);
+  ST* s_accr = reinterpret_cast<ST*>(a.accr);
+  ST* s_acci = reinterpret_cast<ST*>(a.acci);
+  ST* s_outr = reinterpret_cast<ST*>(a.outr);
+  ST* s_outi = reinterpret_cast<ST*>(a.outi);
   // fused: X(I, J) is gathered into Or/Oi; each thread reads its elements
   // there before it writes its outputs to the same places
   __shared__ double gs[TE];
@@ -260,25 +278,25 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     const size_t o = (size_t)ar * ld + b;
     yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
     if (bin && ar < n) {
-      yr_[m] = a.ysr[o];
-      yi_[m] = a.ysi[o];
+      yr_[m] = (double)s_ysr[o];
+      yi_[m] = (double)s_ysi[o];
       if (a.rar) {
-        rr_[m] = a.rar[o];
-        ri_[m] = a.rai[o];
+        rr_[m] = (double)s_rar[o];
+        ri_[m] = (double)s_rai[o];
       }
     }
     if (need_yn) {
-      nr_[m] = a.ynr[o];
-      ni_[m] = a.yni[o];
+      nr_[m] = (double)s_ynr[o];
+      ni_[m] = (double)s_yni[o];
     }
     if (need_acc) {
-      cr_[m] = a.accr[o];
-      ci_[m] = a.acci[o];
+      cr_[m] = (double)s_accr[o];
+      ci_[m] = (double)s_acci[o];
     }
   };
 
   // transposed product tile: Tr[r][c] = X[b0 + r][a0 + c]
-  if constexpr (XS == XS_FUSED32) {
+  if constexpr (XS == XS_FUSED32 || XS == XS_FUSED32S) {
     fused_gather<float>(pv, a.xfr, a.xfi, a0, b0, diag, Tr, Ti, Or, Oi);
   } else if constexpr (FUSED) {
     fused_gather<double>(pv, a.ysr, a.ysi, a0, b0, diag, Tr, Ti, Or, Oi);
@@ -394,15 +412,15 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         outi = ki;
         break;
       case EPI_S1:
-        a.accr[o] = kr;
-        a.acci[o] = ki;
+        s_accr[o] = (ST)kr;
+        s_acci[o] = (ST)ki;
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
       case EPI_S2:
       case EPI_S3:
-        a.accr[o] = cr_[m] + 2.0 * kr;
-        a.acci[o] = ci_[m] + 2.0 * ki;
+        s_accr[o] = (ST)(cr_[m] + 2.0 * kr);
+        s_acci[o] = (ST)(ci_[m] + 2.0 * ki);
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
@@ -441,8 +459,12 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
       outr = 0.0;
       outi = 0.0;
     }
-    a.outr[o] = outr;
-    a.outi[o] = outi;
+    if constexpr (sizeof(ST) == 4) {  // the stored (FP32) value, mirrored below as is
+      outr = (double)(float)outr;
+      outi = (double)(float)outi;
+    }
+    s_outr[o] = (ST)outr;
+    s_outi[o] = (ST)outi;
     if (!diag) {
       Or[r][tx] = outr;
       Oi[r][tx] = outi;
@@ -475,8 +497,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
       const int r = ty + ERS * m;
       const size_t o = (size_t)(b0 + r) * ld + a0 + tx;
       const double outr = Or[tx][r], outi = -Oi[tx][r];
-      a.outr[o] = outr;
-      a.outi[o] = outi;
+      s_outr[o] = (ST)outr;
+      s_outi[o] = (ST)outi;
       if (a.lor) {
         a.lor[o] = (float)outr;
         a.loi[o] = (float)outi;
@@ -1196,6 +1218,21 @@ __global__ void k_axpy_planes(double* __restrict__ yr, double* __restrict__ yi,
   if (p && a == b && a < n) p[a] = vr;
 }
 
+// y += alpha x with x FP32 planes (the fold of the FP32 defect)
+__global__ void k_axpy_planes_f32(double* __restrict__ yr, double* __restrict__ yi,
+                                  const float* __restrict__ xr, const float* __restrict__ xi,
+                                  double alpha, int n, int ld, double* __restrict__ p,
+                                  const DevState* __restrict__ st) {
+  if (st && st->stop) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ld * ld) return;
+  const double vr = yr[idx] + alpha * (double)xr[idx];
+  yr[idx] = vr;
+  yi[idx] = yi[idx] + alpha * (double)xi[idx];
+  const int a = (int)(idx / ld), b = (int)(idx % ld);
+  if (p && a == b && a < n) p[a] = vr;
+}
+
 // y <- y / tr, tr = st->aux[0]
 __global__ void k_scale_planes(double* __restrict__ r, double* __restrict__ im,
                                double* __restrict__ p, int n, int ld,
@@ -1241,20 +1278,23 @@ hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hi
                            bool finish, const FinishJob* carry) {
   const int grid = tri_tiles(pv.ld / TE);
   if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
-  if (carry && a.xkind != XS_FUSED64 && a.xkind != XS_FUSED32) return hipErrorInvalidValue;
+  if (carry && a.xkind != XS_FUSED64 && a.xkind != XS_FUSED32 && a.xkind != XS_FUSED32S)
+    return hipErrorInvalidValue;
   if (a.xkind == XS_DENSE64)
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_DENSE32)
     k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
   else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
     k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else if (a.xkind == XS_FUSED64 || a.xkind == XS_FUSED32) {
+  else if (a.xkind == XS_FUSED64 || a.xkind == XS_FUSED32 || a.xkind == XS_FUSED32S) {
     const FinishJob f = carry ? *carry : FinishJob{};
     const int g = grid + (f.nb > 0 ? 1 : 0), xcd = pv.ld < 4096 ? 1 : 0;
     if (a.xkind == XS_FUSED64)
       k_epilogue_fused<XS_FUSED64><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
-    else
+    else if (a.xkind == XS_FUSED32)
       k_epilogue_fused<XS_FUSED32><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
+    else
+      k_epilogue_fused<XS_FUSED32S><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
   } else {
     return hipErrorInvalidValue;
   }
@@ -1433,6 +1473,14 @@ hipError_t launch_hubs(int n, const double* p, double c, int* out, hipStream_t s
 hipError_t launch_axpy_planes(double* yr, double* yi, const double* xr, const double* xi, double a,
                               int n, int ld, double* p, const DevState* st, hipStream_t s) {
   k_axpy_planes<<<blocks_for((size_t)ld * ld, 256), 256, 0, s>>>(yr, yi, xr, xi, a, n, ld, p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_planes_f32(double* yr, double* yi, const float* xr, const float* xi,
+                                  double a, int n, int ld, double* p, const DevState* st,
+                                  hipStream_t s) {
+  k_axpy_planes_f32<<<blocks_for((size_t)ld * ld, 256), 256, 0, s>>>(yr, yi, xr, xi, a, n, ld, p,
+                                                                     st);
   return hipGetLastError();
 }
 

@@ -92,7 +92,7 @@ class qpr_opts(C.Structure):
                 ("renorm", C.c_int32), ("gemm_cfg", C.c_int32), ("product", C.c_int32),
                 ("integrator", C.c_int32), ("sparse_variant", C.c_int32),
                 ("batch_mode", C.c_int32), ("batch_workers", C.c_int32), ("step_tol", C.c_double),
-                ("dt_max", C.c_double)]
+                ("dt_max", C.c_double), ("delta_state", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -322,13 +322,16 @@ def __getattr__(name):
 BATCH_MODE = {"auto": 0, "persistent": 1, "concurrent": 2}
 
 
+DELTA_STATE = {"auto": 0, "fp64": 1, "fp32": 2}
+
+
 def make_opts(chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1, product="auto",
               integrator="rk4", step_tol=1e-4, dt_max=0.0, sparse_variant=-1, batch_mode="auto",
-              batch_workers=0):
+              batch_workers=0, delta_state="auto"):
     return qpr_opts(int(chunk), int(bool(use_graph)), int(fold_every), int(renorm),
                     int(gemm_cfg), PRODUCT[product], INTEGRATOR[integrator],
                     int(sparse_variant) + 1, BATCH_MODE[batch_mode], int(batch_workers),
-                    float(step_tol), float(dt_max))
+                    float(step_tol), float(dt_max), DELTA_STATE[delta_state], 0)
 
 
 def rhs(P: Problem, omega, rho, prec="fp64", out=None, product="auto", gemm_cfg=-1,
@@ -381,7 +384,7 @@ class SolveResult:
 def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0=None,
                  want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1, gemm_cfg=-1,
                  allow_not_converged=False, product="auto", integrator="rk4", step_tol=1e-4,
-                 dt_max=0.0):
+                 dt_max=0.0, delta_state="auto"):
     torch = _torch()
     n = P.n
     if rho0 is None:
@@ -392,7 +395,7 @@ def steady_state(P: Problem, omega, dt=0.01, tol=1e-8, max_steps=200000, prec="f
     rank = torch.empty(n, dtype=torch.int32, device="cuda") if want_rank else None
     st = qpr_stats()
     op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
-                   dt_max)
+                   dt_max, delta_state=delta_state)
     ws = workspace(n, prec, integrator)
     status = lib().qpr_steady_state(C.byref(P.p), float(omega), float(dt), float(tol),
                                     int(max_steps), PREC[prec], _ptr(rho), _ptr(rank),
@@ -417,7 +420,7 @@ def _pool_streams(k):
 def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", rho0s=None,
                       want_rank=True, chunk=64, use_graph=True, fold_every=0, renorm=1,
                       gemm_cfg=-1, allow_not_converged=False, product="auto", integrator="rk4",
-                      step_tol=1e-4, dt_max=0.0, workers=8):
+                      step_tol=1e-4, dt_max=0.0, workers=8, delta_state="auto"):
     """Solve [(Problem, omega), ...] concurrently with qpr_steady_state_many: a
     pool of min(workers, len(items)) host threads, each with its own stream and
     workspace; each result is bitwise what steady_state returns."""
@@ -442,7 +445,7 @@ def steady_state_many(items, dt=0.01, tol=1e-8, max_steps=200000, prec="fp64", r
             wss.append(workspace(nmax, prec, integrator))
         s.wait_stream(cur)   # the initial states are written on the current stream
     op = make_opts(chunk, use_graph, fold_every, renorm, gemm_cfg, product, integrator, step_tol,
-                   dt_max)
+                   dt_max, delta_state=delta_state)
     probs = (C.POINTER(qpr_problem) * k)(*[C.pointer(P.p) for P, _ in items])
     omegas = (C.c_double * k)(*[float(w) for _, w in items])
     rho_ptrs = (C.c_void_p * k)(*[r.data_ptr() for r in rhos])
@@ -605,7 +608,7 @@ class BatchResult:
 def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=None,
                 want_rank=True, chunk=0, use_graph=True, gemm_cfg=-1, product="auto",
                 allow_not_converged=False, integrator="rk4", step_tol=1e-4, dt_max=0.0,
-                mode="auto", workers=0):
+                mode="auto", workers=0, delta_state="auto"):
     """Solve [(Problem, omega), ...] together with qpr_batch_solve (mode "auto" or
     "concurrent": a pool of worker streams; "persistent": shared launches).
     chunk 0 takes the library's default for the mode."""
@@ -614,7 +617,7 @@ def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=N
     nsys = len(items)
     ns = (C.c_int32 * nsys)(*[P.n for P, _ in items])
     op = make_opts(chunk, use_graph, 0, 1, gemm_cfg, product, integrator, step_tol, dt_max,
-                   batch_mode=mode, batch_workers=workers)
+                   batch_mode=mode, batch_workers=workers, delta_state=delta_state)
     nbytes = lib().qpr_batch_workspace_bytes(nsys, ns, PREC[prec], C.byref(op))
     if nbytes == 0:
         raise QprError(QPR_E_ARG, "invalid batch request")

@@ -47,8 +47,10 @@ def test_lowp_rhs_error_bound(Q, prec, product, n, m, omega):
 
 
 @pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "fused"), ("fp32", "dense"),
-                                          ("bf16x3", "dense")])
+                                          ("bf16x3", "dense"), ("fp32", "auto")])
 def test_mixed_steady_state_matches_oracle(Q, prec, product):
+    """("fp32", "auto") is the defect held in FP32 (every state plane of the
+    steps single precision); the explicit products keep it in FP64."""
     g = inputs.ba_digraph(130, 3, seed=1)
     P = Q.Problem.from_graph(g)
     R = O.problem_ref(g.n, g.src, g.dst)
@@ -78,7 +80,7 @@ def test_mixed_steady_state_matches_oracle(Q, prec, product):
 
 
 @pytest.mark.parametrize("prec,product", [("fp32", "sparse"), ("fp32", "fused"), ("fp32", "dense"),
-                                          ("bf16x3", "dense")])
+                                          ("bf16x3", "dense"), ("fp32", "auto")])
 def test_mixed_n922_against_fp64_gpu(Q, prec, product):
     g = inputs.ba_digraph(922, 3, seed=0)
     P = Q.Problem.from_graph(g)
@@ -148,3 +150,33 @@ def test_fp32_fused_equals_fp32_sparse_bitwise(Q, name, n, m):
     b = Q.steady_state(P, 0.7, 0.01, tol, 400000, prec="fp32", product="fused", fold_every=50)
     assert torch.equal(a.rho, b.rho)
     assert a.stats["steps"] == b.stats["steps"] and a.stats["folds"] == b.stats["folds"]
+
+
+@pytest.mark.parametrize("n,m,omega", [(70, 2, 0.3), (130, 3, 0.6), (300, 2, 0.9)])
+def test_fp32_defect_state_matches_fp64_defect_state(Q, n, m, omega):
+    """The same defect correction with the defect held in FP32 and in FP64:
+    both converge to the oracle-measured tolerance, agree within the mixed
+    bound, and the FP32-state solve is bitwise Hermitian and trace one."""
+    g = inputs.ba_digraph(n, m, seed=n + 1)
+    P = Q.Problem.from_graph(g)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    f = lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, omega)
+    a = Q.steady_state(P, omega, 0.01, 1e-9, 400000, prec="fp32", delta_state="fp32",
+                       product="sparse")
+    b = Q.steady_state(P, omega, 0.01, 1e-9, 400000, prec="fp32", delta_state="fp64",
+                       product="fused")
+    ra, rb = Q.to_complex(a.rho), Q.to_complex(b.rho)
+    for r in (ra, rb):
+        assert np.sqrt(np.sum(np.abs(f(r)) ** 2)) < 1e-9 * (1 + 1e-6)
+    assert np.max(np.abs(ra - rb)) < 1e-6
+    assert a.stats["herm_err"] == 0.0 and a.stats["trace_err"] < 1e-12
+    assert a.stats["converged"] == 1 and a.stats["folds"] >= 2
+
+
+def test_fp32_defect_state_option_errors(Q):
+    P = Q.Problem.from_graph(inputs.ba_digraph(130, 3, seed=1))
+    with pytest.raises(Q.QprError):   # an FP32 defect needs the sparse product
+        Q.steady_state(P, 0.5, 0.01, 1e-8, 1000, prec="fp32", product="dense",
+                       delta_state="fp32")
+    with pytest.raises(Q.QprError):   # and the FP32 product
+        Q.steady_state(P, 0.5, 0.01, 1e-8, 1000, prec="bf16x3", delta_state="fp32")

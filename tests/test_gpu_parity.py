@@ -399,7 +399,7 @@ def test_permutation_equivariance(Q, product):
 
 
 @pytest.mark.parametrize("product,prec", [("sparse", "fp64"), ("fused", "fp64"),
-                                          ("dense", "fp64"), ("fused", "fp32")])
+                                          ("dense", "fp64"), ("fused", "fp32"), ("auto", "fp32")])
 def test_runs_are_bitwise_reproducible(Q, product, prec):
     """Fixed-order reductions, no atomics on values: the same solve twice gives
     the same bits (state, steps, residual)."""
