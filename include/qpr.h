@@ -178,11 +178,16 @@ typedef enum {
                              and in qpr_steady_state_many while two or more systems run */
   QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
   QPR_PRODUCT_SPARSE = 2, /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
-  QPR_PRODUCT_FUSED = 3   /* the same gathers inside the epilogue: each tile pair gathers the two
+  QPR_PRODUCT_FUSED = 3,  /* the same gathers inside the epilogue: each tile pair gathers the two
                              32 x 32 blocks of X it needs into LDS, so X never goes to HBM and a
                              stage is one launch; bitwise the SPARSE stage.  The FP32 steps
                              of the mixed solve gather the FP32 copy of the state the same way
                              (X rounded once to FP32, as the separate FP32 product) */
+  QPR_PRODUCT_BLOCKSPARSE = 4 /* the MFMA product with tile skipping: each 32-row block of H_off
+                             multiplies only the 16-wide k-slabs in which it has a nonzero (slab
+                             lists built from the CSR pattern at the start of the call); equal to
+                             the dense product.  QPR_FP64 and QPR_FP32 (FP32 operands); not the
+                             persistent batch form */
 } qpr_product;
 
 /* How qpr_batch_solve runs its systems. */
@@ -449,8 +454,12 @@ qpr_status qpr_mpnn_adam(float* params, const float* grads, float* m, float* v,
  * both planes per wave, R rows per wave), 4 row128 (one workgroup per row and
  * 128-column chunk).  The default is row128 below N = 1536 and cm_w128_r1 above where
  * the padded size is a multiple of 128.  All variants give bitwise the same
- * product.  With QPR_FP64, v = qpr_sparse_variants() times the fused
- * epilogue of QPR_PRODUCT_FUSED (no product launch: ms_out[0] = 0).
+ * product.  With QPR_FP64 or QPR_FP32, v = qpr_sparse_variants() times the
+ * fused epilogue of QPR_PRODUCT_FUSED (no product launch: ms_out[0] = 0);
+ * v = qpr_sparse_variants() + 1 times the block-sparse product of
+ * QPR_PRODUCT_BLOCKSPARSE in place of the dense one; with QPR_FP32,
+ * v = qpr_sparse_variants() + 2 times the fused stages of the defect held in
+ * FP32 (opts delta_state; no product launch).
  *   rho     device, 2*n*n planar FP64 operand (unchanged)
  *   ms_out  HOST double[2]: mean milliseconds per product launch and per
  *           epilogue launch (the mean over the four stages)

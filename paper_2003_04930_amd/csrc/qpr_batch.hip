@@ -216,6 +216,8 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   if (o.batch_mode < QPR_BATCH_AUTO || o.batch_mode > QPR_BATCH_CONCURRENT)
     return fail(QPR_E_ARG, "unknown batch_mode %d", o.batch_mode);
   const bool concurrent = batch_concurrent(&o);
+  if (!concurrent && o.product == QPR_PRODUCT_BLOCKSPARSE)
+    return fail(QPR_E_ARG, "the persistent batch form has no block-sparse product");
   if (o.chunk <= 0) o.chunk = concurrent ? 64 : 32;
   const bool rkf = o.integrator == QPR_RKF45;
   if (rkf && prec != QPR_FP64) return fail(QPR_E_ARG, "the RKF45 integrator runs in FP64 only");

@@ -11,6 +11,10 @@
 namespace qpr {
 
 constexpr int kPad = 64;          // internal planes are padded to a multiple of this
+// block-sparse product: slab lists per 32-row block of H_off, slabs 16 wide
+constexpr int kBsM = 32, kBsK = 16;
+// product configuration value that selects the block-sparse product
+constexpr int kCfgBlockSparse = -1000;
 constexpr size_t kAlign = 256;    // every carved region starts on this boundary
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -130,6 +134,7 @@ struct Ws {
   double *cand_r = nullptr, *cand_i = nullptr, *p_c = nullptr;  // Fehlberg candidate state
   double* partials = nullptr;                // per-workgroup partial sums
   int max_partials = 0;
+  int *bs_cnt = nullptr, *bs_idx = nullptr;  // block-sparse product: slab lists per block row
   DevState* st = nullptr;
   double* scal = nullptr;                    // small scratch (16 doubles)
 };
@@ -204,8 +209,11 @@ struct EpiArgs {
   double ce[6];                 // stage 6: b5 - b4
 };
 
+// cfg = kCfgBlockSparse: the block-sparse product over the slab lists in w
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w,
                        const double* yr, const double* yi, int gate, hipStream_t s);
+// slab lists of the block-sparse product for P into w.bs_cnt / w.bs_idx
+hipError_t launch_block_pattern(const qpr_problem* P, const Ws& w, hipStream_t s);
 // finish = false leaves a reducing stage's partials unfolded (kernel timing,
 // or a finishing step carried by the next launch); `carry` (fused epilogue
 // only) is the previous stage's finishing step, run as one extra workgroup

@@ -64,10 +64,18 @@ struct MfmaK4<float> {
 };
 
 // One BM x BN output tile (both planes) at (m0, n0).
+// With `slabs` set, only the nslabs k-slabs it lists (slab j = k rows
+// [j BK, j BK + BK), ascending) are multiplied: the block-sparse product skips
+// the slabs in which this tile's BM rows of H_off are all zero.  Every output
+// element still accumulates its slabs in ascending k with the same MFMA
+// sequence, and a skipped slab would only have added exact zeros, so the
+// result equals the dense product's.
 template <typename T, int BM, int BN, int WM, int WN, int BK>
 __device__ __forceinline__ void gemm_k4_tile(const T* __restrict__ H, const T* __restrict__ Yr,
                                              const T* __restrict__ Yi, T* __restrict__ Xr,
-                                             T* __restrict__ Xi, int ld, int m0, int n0) {
+                                             T* __restrict__ Xi, int ld, int m0, int n0,
+                                             const int* __restrict__ slabs = nullptr,
+                                             int nslabs = 0) {
   typedef MfmaK4<T> M;
   typedef typename M::acc_t acc_t;
   typedef typename M::vec_t vec_t;
@@ -125,14 +133,17 @@ __device__ __forceinline__ void gemm_k4_tile(const T* __restrict__ H, const T* _
     }
   };
 
-  const int KT = ld / BK;
-  gload(0);
-  lstore(0);
+  const int KT = slabs ? nslabs : ld / BK;
+  auto kofs = [&](int kt) { return (slabs ? slabs[kt] : kt) * BK; };
+  if (KT > 0) {
+    gload(kofs(0));
+    lstore(0);
+  }
   __syncthreads();
   const int lr = lane >> 4, lc = lane & 15;
   for (int kt = 0; kt < KT; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < KT) gload((kt + 1) * BK);
+    if (kt + 1 < KT) gload(kofs(kt + 1));
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[FM], b[2][FN];
@@ -180,6 +191,48 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   gemm_k4_tile<T, BM, BN, WM, WN, BK>(H, Yr, Yi, Xr, Xi, ld, (logical % tiles_m) * BM,
                                       (logical / tiles_m) * BN);
+}
+
+// Block-sparse tile-skipping product (BM = 32 rows of H_off per tile, the
+// granularity of the slab lists): tile (m0, n0) multiplies only the k-slabs
+// of width BK listed for its block row, cnt[m0 / 32] of them at
+// idx[(m0 / 32) * (ld / BK) ..] (built by k_block_pattern).
+template <typename T, int BN, int WM, int WN, int BK>
+__global__ void __launch_bounds__((32 / WM) * (BN / WN) * 64)
+    k_gemm_k4_bs(const T* __restrict__ H, const T* __restrict__ Yr, const T* __restrict__ Yi,
+                 T* __restrict__ Xr, T* __restrict__ Xi, int ld, const int* __restrict__ cnt,
+                 const int* __restrict__ idx, const DevState* __restrict__ st, int gate) {
+  if (st->stop || (gate && st->hold)) return;
+  constexpr int BM = 32;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int mb = logical % tiles_m;
+  gemm_k4_tile<T, BM, BN, WM, WN, BK>(H, Yr, Yi, Xr, Xi, ld, mb * BM, (logical / tiles_m) * BN,
+                                      idx + (size_t)mb * (ld / BK), cnt[mb]);
+}
+
+// The slab lists of the block-sparse product: workgroup mb marks the k-slabs
+// (width kBsK) holding a nonzero of rows [32 mb, 32 mb + 32) of H_off (from
+// its CSR pattern) in LDS, then lists them in ascending order.
+__global__ void __launch_bounds__(256) k_block_pattern(const int* __restrict__ h_ptr,
+                                                        const int* __restrict__ h_idx, int n,
+                                                        int ld, int* __restrict__ cnt,
+                                                        int* __restrict__ idx) {
+  extern __shared__ int flag[];
+  const int mb = blockIdx.x, ks = ld / kBsK;
+  for (int j = threadIdx.x; j < ks; j += blockDim.x) flag[j] = 0;
+  __syncthreads();
+  const int r0 = mb * kBsM, r1 = min(r0 + kBsM, n);
+  if (r0 < n)
+    for (int e = h_ptr[r0] + threadIdx.x; e < h_ptr[r1]; e += blockDim.x) flag[h_idx[e] / kBsK] = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    int* out = idx + (size_t)mb * ks;
+    for (int j = 0; j < ks; ++j)
+      if (flag[j]) out[c++] = j;
+    cnt[mb] = c;
+  }
 }
 
 // Persistent form for many systems: the grid strides over a device-side list
@@ -477,6 +530,17 @@ const GemmCfg<BFFn> kBF[] = {
     {128, 128, "bf16x3_128x128_w64x64_sb", k_gemm_bf16x3_sb<128, 128, 64, 64>, 256},
     {256, 128, "bf16x3_256x128_w64x64_sb", k_gemm_bf16x3_sb<256, 128, 64, 64>, 512},
 };
+// block-sparse tiles: 32 rows (the slab-list granularity) x BN columns
+typedef void (*F64BsFn)(const double*, const double*, const double*, double*, double*, int,
+                        const int*, const int*, const DevState*, int);
+typedef void (*F32BsFn)(const float*, const float*, const float*, float*, float*, int,
+                        const int*, const int*, const DevState*, int);
+// (32 x 64 keeps three waves per SIMD; a 32 x 128 tile needs 86 KB of LDS
+// for its double-buffered operands, one workgroup per CU)
+const GemmCfg<F64BsFn> kF64Bs = {32, 64, "f64_bs_32x64_w16x32_k16",
+                                 k_gemm_k4_bs<double, 64, 16, 32, kBsK>, 256};
+const GemmCfg<F32BsFn> kF32Bs = {32, 64, "f32_bs_32x64_w32x32_k16",
+                                 k_gemm_k4_bs<float, 64, 32, 32, kBsK>, 128};
 constexpr int kNumF64 = sizeof(kF64) / sizeof(kF64[0]);
 constexpr int kNumF32 = sizeof(kF32) / sizeof(kF32[0]);
 constexpr int kNumBF = sizeof(kBF) / sizeof(kBF[0]);
@@ -557,8 +621,34 @@ static int pick(const C* table, int count, int cfg, int kind, int n, int ld) {
   return cfg;  // configuration 0 tiles 64 x 64, which divides every ld
 }
 
+hipError_t launch_block_pattern(const qpr_problem* P, const Ws& w, hipStream_t s) {
+  const int ld = P->ld;
+  k_block_pattern<<<ld / kBsM, 256, (size_t)(ld / kBsK) * sizeof(int), s>>>(
+      P->h_ptr, P->h_idx, P->n, ld, w.bs_cnt, w.bs_idx);
+  return hipGetLastError();
+}
+
+// The block-sparse product: 32 x 64 tiles (ld is a multiple of 64).
+static hipError_t launch_gemm_bs(int kind, const qpr_problem* P, const Ws& w, const double* yr,
+                                 const double* yi, int gate, hipStream_t s) {
+  const int ld = P->ld;
+  if (kind == OP_F64) {
+    hipLaunchKernelGGL(kF64Bs.fn, dim3((ld / 32) * (ld / kF64Bs.bn)), dim3(kF64Bs.threads), 0, s,
+                       P->h_off, yr, yi, w.x_r, w.x_i, ld, w.bs_cnt, w.bs_idx, w.st, gate);
+    return hipGetLastError();
+  }
+  if (kind == OP_F32) {
+    hipLaunchKernelGGL(kF32Bs.fn, dim3((ld / 32) * (ld / kF32Bs.bn)), dim3(kF32Bs.threads), 0, s,
+                       P->h_off_f32, (const float*)w.lo_r, (const float*)w.lo_i, w.xf_r, w.xf_i,
+                       ld, w.bs_cnt, w.bs_idx, w.st, gate);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;  // no block-sparse form of the three-slice bf16 product
+}
+
 hipError_t launch_gemm(int kind, int cfg, const qpr_problem* P, const Ws& w, const double* yr,
                        const double* yi, int gate, hipStream_t s) {
+  if (cfg == kCfgBlockSparse) return launch_gemm_bs(kind, P, w, yr, yi, gate, s);
   const int ld = P->ld;
   if (kind == OP_F64) {
     const auto& c = kF64[pick(kF64, kNumF64, cfg, kind, P->n, ld)];

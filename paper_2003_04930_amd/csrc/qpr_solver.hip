@@ -40,7 +40,8 @@ void clear_error() { g_err[0] = 0; }
 // The fused mode asks for the same gathers, so it implies the sparse product
 // wherever the fused epilogue does not apply (the FP32 product).
 static bool use_sparse(const qpr_problem* P, int product, int xk) {
-  if (xk == OP_BF16X3 || product == QPR_PRODUCT_DENSE) return false;
+  if (xk == OP_BF16X3 || product == QPR_PRODUCT_DENSE || product == QPR_PRODUCT_BLOCKSPARSE)
+    return false;
   if (product == QPR_PRODUCT_SPARSE || product == QPR_PRODUCT_FUSED) return true;
   return (double)P->nnz_h < 0.05 * (double)P->n * (double)P->n;
 }
@@ -91,10 +92,25 @@ static int op_kind(int prec) {
   return prec == QPR_FP32 ? OP_F32 : prec == QPR_BF16X3 ? OP_BF16X3 : OP_F64;
 }
 
+// QPR_PRODUCT_BLOCKSPARSE: build the slab lists of H_off in the workspace and
+// route every product of the call to the tile-skipping kernels (the dense
+// product's role: use_sparse() is false for it).
+static qpr_status setup_product(const qpr_problem* P, const Ws& w, int prec, qpr_opts* o,
+                                hipStream_t s) {
+  if (o->product < QPR_PRODUCT_AUTO || o->product > QPR_PRODUCT_BLOCKSPARSE)
+    return fail(QPR_E_ARG, "unknown product %d", o->product);
+  if (o->product != QPR_PRODUCT_BLOCKSPARSE) return QPR_OK;
+  if (prec == QPR_BF16X3)
+    return fail(QPR_E_ARG, "the block-sparse product serves QPR_FP64 and QPR_FP32");
+  QPR_HIP(launch_block_pattern(P, w, s));
+  o->gemm_cfg = kCfgBlockSparse;
+  return QPR_OK;
+}
+
 // ---------------------------------------------------------------- workspace
 namespace {
 struct WsLayout {
-  size_t yn, y1, y2, acc, x, ra, an, xf, lo, sl, pv, kf, cand, pc, partials, st, scal, total;
+  size_t yn, y1, y2, acc, x, ra, an, xf, lo, sl, pv, kf, cand, pc, partials, st, scal, bs, total;
   int max_partials;
 };
 
@@ -127,6 +143,9 @@ WsLayout ws_layout(int n, int prec, bool rkf) {
   L.partials = take((size_t)L.max_partials * 8);
   L.st = take(sizeof(DevState));
   L.scal = take(16 * 8);
+  // block-sparse product: a slab count per 32-row block and a list of up to
+  // ld / 16 slabs each
+  L.bs = take((ld / kBsM) * 4 + (ld / kBsM) * (ld / kBsK) * 4);
   L.total = o;
   return L;
 }
@@ -196,6 +215,8 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
   w->max_partials = L.max_partials;
   w->st = (DevState*)(b + L.st);
   w->scal = (double*)(b + L.scal);
+  w->bs_cnt = (int*)(b + L.bs);
+  w->bs_idx = w->bs_cnt + ld / kBsM;
   return true;
 }
 
@@ -554,7 +575,7 @@ static qpr_opts default_opts() {
 extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* rho, double* out,
                               int32_t prec, const qpr_opts* opts, void* ws, size_t wsb,
                               qpr_stream_t stream) {
-  const qpr_opts o = opts ? *opts : default_opts();
+  qpr_opts o = opts ? *opts : default_opts();
   clear_error();
   Ws w;
   qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
@@ -564,6 +585,7 @@ extern "C" qpr_status qpr_rhs(const qpr_problem* P, double omega, const double* 
   hipStream_t s = (hipStream_t)stream;
   ProbView pv;
   if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
+  if ((st = setup_product(P, w, prec, &o, s)) != QPR_OK) return st;
   QPR_HIP(launch_state_init(w.st, 0.0, 0, 0, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
   QPR_HIP(enqueue_rhs(P, w, pv, omega, w.y1_r, w.y1_i, w.p_1, w.y2_r, w.y2_i, op_kind(prec), o.gemm_cfg,
@@ -576,7 +598,7 @@ extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt
                                    double* rho, int32_t prec, double* diag_out,
                                    const qpr_opts* opts, void* ws, size_t wsb,
                                    qpr_stream_t stream) {
-  const qpr_opts o = opts ? *opts : default_opts();
+  qpr_opts o = opts ? *opts : default_opts();
   clear_error();
   Ws w;
   qpr_status st = check_common(P, omega, prec, ws, wsb, &w);
@@ -587,6 +609,7 @@ extern "C" qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt
   hipStream_t s = (hipStream_t)stream;
   ProbView pv;
   if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
+  if ((st = setup_product(P, w, prec, &o, s)) != QPR_OK) return st;
   const int xk = op_kind(prec);
   QPR_HIP(launch_state_init(w.st, 0.0, nsteps, 0, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
@@ -743,6 +766,7 @@ static qpr_status steady_state_impl(const qpr_problem* P, double omega, double d
   hipStream_t s = (hipStream_t)stream;
   ProbView pv;
   if ((st = view_for(P, o, &pv)) != QPR_OK) return st;
+  if ((st = setup_product(P, w, prec, &o, s)) != QPR_OK) return st;
   const int n = P->n, ld = P->ld;
   qpr_stats S{};
   qpr_status result = QPR_OK;
@@ -1078,17 +1102,38 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   QPR_HIP(launch_fill(w.acc_r, 2 * (size_t)P->ld * P->ld * 8, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
   // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v;
-  // v = the number of variants: the fused epilogue (no product launch)
-  const bool sparse = cfg <= -2 && xk != OP_BF16X3;
+  // v = nvar (the number of variants): the fused epilogue (no product launch);
+  // v = nvar + 1: the block-sparse MFMA product; v = nvar + 2 (QPR_FP32): the
+  // fused stages of the FP32-state defect (no product launch)
+  const int nvar = spmm_num_variants();
   const int spv = cfg <= -3 ? -3 - cfg : -1;
-  const bool fused = sparse && spv == spmm_num_variants();
-  if (sparse && spv > spmm_num_variants() - (fused ? 0 : 1))
-    return fail(QPR_E_ARG, "no such sparse-product variant");
-  const int xs = fused ? (xk == OP_F64 ? XS_FUSED64 : XS_FUSED32)
-                       : xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
+  if (spv > nvar + 2) return fail(QPR_E_ARG, "no such sparse-product variant");
+  const bool bsp = spv == nvar + 1;
+  const bool f32s = spv == nvar + 2;
+  if (bsp && xk == OP_BF16X3) return fail(QPR_E_ARG, "no block-sparse bf16 product");
+  if (f32s && xk != OP_F32) return fail(QPR_E_ARG, "the FP32-state stages need QPR_FP32");
+  const bool sparse = cfg <= -2 && xk != OP_BF16X3 && !bsp;
+  const bool fused = sparse && (spv == nvar || f32s);
+  if (bsp) {
+    QPR_HIP(launch_block_pattern(P, w, s));
+    cfg = kCfgBlockSparse;
+  }
+  const int xs = f32s ? XS_FUSED32S
+                      : fused ? (xk == OP_F64 ? XS_FUSED64 : XS_FUSED32)
+                              : xk != OP_F64 ? XS_DENSE32 : sparse ? XS_SPARSE64 : XS_DENSE64;
   // the FP32 fused stages gather from both FP32 copies in turn (the X planes
   // hold the second one)
-  if (fused && xk == OP_F32) QPR_HIP(launch_fill(w.xf_r, 2 * (size_t)P->ld * P->ld * 4, s));
+  if (fused && xk == OP_F32 && !f32s)
+    QPR_HIP(launch_fill(w.xf_r, 2 * (size_t)P->ld * P->ld * 4, s));
+  if (f32s) {  // FP32 state planes: the operand (as the FP32 copy) and zeros
+    const size_t pl4 = 2 * (size_t)P->ld * P->ld * 4;
+    QPR_HIP(launch_to_lowp(OP_F32, w.y1_r, w.y1_i, P->n, P->ld, w, s));
+    QPR_HIP(launch_fill(w.dac_r, pl4, s));
+    QPR_HIP(launch_fill(w.ra32_r, pl4, s));
+    QPR_HIP(hipMemcpyAsync(w.dn_r, w.lo_r, pl4, hipMemcpyDeviceToDevice, s));
+    QPR_HIP(hipMemcpyAsync(w.d1_r, w.lo_r, pl4, hipMemcpyDeviceToDevice, s));
+    QPR_HIP(hipMemcpyAsync(w.d2_r, w.lo_r, pl4, hipMemcpyDeviceToDevice, s));
+  }
   HipEvent evh[3];
   for (auto& e : evh) QPR_HIP(hipEventCreate(&e.h));
   hipEvent_t ev[3] = {evh[0].h, evh[1].h, evh[2].h};
@@ -1103,7 +1148,9 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   // computes its reductions, the finishing kernel that folds them is not timed
   for (int r = 0; r < reps; ++r)
     for (int k = 0; k < 4; ++k)
-      QPR_HIP(launch_epilogue(pv, rk4_stage_args(w, k, omega, 0.01, xk, xs, CHK_PLAIN, 0, false),
+      QPR_HIP(launch_epilogue(pv,
+                              f32s ? rk4_stage_args_f32s(w, k, omega, 0.01, CHK_PLAIN, 0)
+                                   : rk4_stage_args(w, k, omega, 0.01, xk, xs, CHK_PLAIN, 0, false),
                               w, s, false));
   QPR_HIP(hipEventRecord(ev[2], s));
   QPR_HIP(hipEventSynchronize(ev[2]));

@@ -14,8 +14,10 @@ Kernels: sparse (FP64 sparse product plus the epilogues of the four RK4
 stages; --variant picks the sparse-product kernel variant, default the
 library's), fused (the fused epilogue of the four stages, gathers inside),
 fp32sparse (the FP32-operand sparse product of the mixed solve),
-dense (FP64 MFMA product), bf16x3 / fp32 (low-precision MFMA products); each
-followed by the epilogues of `reps` RK4 steps.
+fused32s (the fused stages of the mixed solve with the defect held in FP32),
+dense (FP64 MFMA product), blocksparse / blocksparse32 (the tile-skipping MFMA
+product, FP64 / FP32 operands), bf16x3 / fp32 (low-precision MFMA products);
+each followed by the epilogues of `reps` RK4 steps.
 """
 from __future__ import annotations
 
@@ -31,7 +33,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=922)
     ap.add_argument("--kernel", default="sparse",
-                    choices=["sparse", "fused", "fp32sparse", "dense", "fp32", "bf16x3"])
+                    choices=["sparse", "fused", "fp32sparse", "fused32s", "dense", "fp32", "bf16x3",
+                             "blocksparse", "blocksparse32"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=256)
     ap.add_argument("--variant", type=int, default=-1,
@@ -43,12 +46,18 @@ def main():
     g = inputs.ba_digraph(args.n, 3 if args.n <= 1000 else 4, seed=0)
     P = Q.Problem.from_graph(g)
     rho = Q.planar(inputs.random_density(args.n, seed=1))
-    prec = {"sparse": "fp64", "fused": "fp64", "dense": "fp64",
-            "fp32sparse": "fp32"}.get(args.kernel, args.kernel)
+    prec = {"sparse": "fp64", "fused": "fp64", "dense": "fp64", "blocksparse": "fp64",
+            "fp32sparse": "fp32", "fused32s": "fp32", "blocksparse32": "fp32"}.get(args.kernel,
+                                                                                  args.kernel)
     sparse = args.kernel in ("sparse", "fp32sparse")
     cfg = (-2 if args.variant < 0 else -3 - args.variant) if sparse else -1
+    nvar = len(Q.SPARSE_VARIANTS)
     if args.kernel == "fused":  # the fused epilogue alone (no product launch)
-        cfg = -3 - len(Q.SPARSE_VARIANTS)
+        cfg = -3 - nvar
+    if args.kernel in ("blocksparse", "blocksparse32"):
+        cfg = -3 - (nvar + 1)
+    if args.kernel == "fused32s":
+        cfg = -3 - (nvar + 2)
     prod_ms, epi_ms = Q.time_kernels(P, 0.8, rho, prec=prec, cfg=cfg, reps=args.reps)
     nbytes = args.copy_mb << 20
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)

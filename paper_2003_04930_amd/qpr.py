@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "QPR_OK", -1: "QPR_E_ARG", -2: "QPR_E_HIP", -3: "QPR_E_NOT_CO
 TELEPORT = {"paper_f": 0, "uniform": 1}
 HDIAG = {"zero": 0, "paper": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-PRODUCT = {"auto": 0, "dense": 1, "sparse": 2, "fused": 3}
+PRODUCT = {"auto": 0, "dense": 1, "sparse": 2, "fused": 3, "blocksparse": 4}
 INTEGRATOR = {"rk4": 0, "rkf45": 1}
 
 # every symbol include/qpr.h declares

@@ -72,7 +72,7 @@ def test_build_matches_oracle(Q, name, teleport, hdiag):
 
 
 # --------------------------------------------------------------------- rhs
-@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused", "blocksparse"])
 @pytest.mark.parametrize("name", sorted(GRAPHS))
 @pytest.mark.parametrize("omega", [0.0, 0.35, 0.8, 1.0])
 def test_rhs_fp64_matches_oracle(Q, name, omega, product):
@@ -88,7 +88,7 @@ def test_rhs_fp64_matches_oracle(Q, name, omega, product):
 
 
 # -------------------------------------------------------------- RK4 steps
-@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused", "blocksparse"])
 @pytest.mark.parametrize("name,steps", [("er16", 60), ("er70", 25), ("ba130", 12)])
 def test_rk4_steps_step_locked(Q, name, steps, product):
     g = GRAPHS[name]()
@@ -135,7 +135,7 @@ def test_steady_state_graph_and_chunking_do_not_change_result(Q, chunk, use_grap
     assert torch.equal(out.rho, ref.rho)
 
 
-@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused", "blocksparse"])
 def test_steady_state_ba130_properties_and_oracle(Q, product):
     g = GRAPHS["ba130"]()
     P = Q.Problem.from_graph(g)
@@ -183,7 +183,7 @@ def test_error_paths(Q):
 
 
 # ------------------------------------------------------ Fehlberg RKF45
-@pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
+@pytest.mark.parametrize("product", ["dense", "sparse", "fused", "blocksparse"])
 def test_rkf45_attempts_match_oracle(Q, product):
     """The first attempts of the adaptive Fehlberg integration: same accepted
     and rejected counts and the same state as the oracle's RKF45."""
@@ -374,7 +374,7 @@ def test_steady_state_n922_properties(Q, omega):
     assert np.max(np.abs(Q.to_complex(x) - want)) < 1e-12
 
 
-@pytest.mark.parametrize("product", ["sparse", "fused", "dense"])
+@pytest.mark.parametrize("product", ["sparse", "fused", "dense", "blocksparse"])
 def test_permutation_equivariance(Q, product):
     """Relabelling the nodes permutes everything: L(P rho P^T) = P L(rho) P^T
     for the relabelled graph, the steady state is the permuted one and the
@@ -408,3 +408,38 @@ def test_runs_are_bitwise_reproducible(Q, product, prec):
     b = Q.steady_state(P, 0.45, 0.01, 1e-9, 200000, prec=prec, product=product)
     assert torch.equal(a.rho, b.rho) and torch.equal(a.rank, b.rank)
     assert a.stats["steps"] == b.stats["steps"] and a.stats["residual"] == b.stats["residual"]
+
+
+def _hub_graph_or(name):
+    return (_hub_and_isolated() if name == "hub_isolated" else
+            inputs.ba_digraph(922, 3, seed=0) if name == "ba922" else
+            inputs.ba_digraph(1000, 4, seed=2) if name == "ba1000" else GRAPHS[name]())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["er16", "er70", "ba130", "hub_isolated", "ba922", "ba1000"])
+def test_blocksparse_equals_dense(Q, name, prec):
+    """The tile-skipping product multiplies only the k-slabs in which a 32-row
+    block of H_off has a nonzero; the slabs it skips would only add exact
+    zeros, so the right-hand side and RK4 steps equal the dense product's
+    (graphs with empty rows, a 189-entry row, ragged tiles, ld = 960 and
+    1024 (32 x 64 and 32 x 128 tiles))."""
+    g = _hub_graph_or(name)
+    P = Q.Problem.from_graph(g)
+    rho = Q.planar(inputs.random_density(g.n, seed=41))
+    a = Q.rhs(P, 0.55, rho, prec=prec, product="dense")
+    b = Q.rhs(P, 0.55, rho, prec=prec, product="blocksparse")
+    assert torch.equal(a, b)
+    xa, xb = rho.clone(), rho.clone()
+    Q.rk4_step(P, 0.55, 0.01, 3, xa, prec=prec, product="dense")
+    Q.rk4_step(P, 0.55, 0.01, 3, xb, prec=prec, product="blocksparse")
+    assert torch.equal(xa, xb)
+
+
+def test_blocksparse_rejections(Q):
+    P = Q.Problem.from_graph(GRAPHS["ba130"]())
+    rho = Q.planar(inputs.random_density(130, seed=2))
+    with pytest.raises(Q.QprError):
+        Q.rhs(P, 0.5, rho, prec="bf16x3", product="blocksparse")
+    with pytest.raises(Q.QprError):
+        Q.batch_solve([(P, 0.5)], product="blocksparse", mode="persistent")
