@@ -62,6 +62,18 @@ def measured_traffic(kernel):
     return TRAFFIC_N922.get(kernel)
 
 
+def _json_default(o):
+    """numpy scalars in the extra rows"""
+    import numpy as np
+    if isinstance(o, np.integer):
+        return int(o)
+    if isinstance(o, np.floating):
+        return float(o)
+    if isinstance(o, np.bool_):
+        return bool(o)
+    raise TypeError(f"not JSON serialisable: {type(o).__name__}")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -261,6 +273,14 @@ def n4096_rows(Q, inputs, params, torch, np, args):
             # mixed precision from the learned warm start (inference included)
             runs["mixed_fp32_warm"] = lambda: Q.steady_state(
                 Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), prec="fp32")
+
+            # the spec form: qpr_batch_solve, FP32 steps with the FP64
+            # fold and judge, from the learned warm start (inference included)
+            def batch_warm():
+                rb = Q.batch_solve([(Pn, w)], tol=TOL, prec="fp32",
+                                   rho0s=W.warm_rho0_batch([(Pn, w)], params))
+                return Q.SolveResult(rb.rhos[0], rb.ranks[0], rb.stats[0], rb.status)
+            runs["batch_mixed_fp32_warm"] = batch_warm
     for name, fn in runs.items():
         t0 = time.perf_counter()
         r = fn()
@@ -274,7 +294,69 @@ def n4096_rows(Q, inputs, params, torch, np, args):
                      "order_violations_beyond_2maxdrho":
                          tie_aware_rank_check(p_ref, r.rank.cpu().numpy(), 2 * err, np)}
         log(f"n=4096 {name}: {t:.2f} s ({plain.stats['seconds'] / t:.1f}x), max|drho| {err:.1e}")
+    # hub classes and degeneracy of PageRank against the quantum steady state
+    # (tie resolution: twice the spread of two independent solves)
+    from paper_2003_04930_amd import study
+    tau = 2 * row.get("fp64_rkf45", {}).get("max_abs_drho_vs_plain", 5e-8)
+    row["study"] = study.hub_study(Q, Pn, plain.rho, tau)
     return row
+
+
+def n2048_rows(Q, inputs, torch, np):
+    """BA graph N = 2048 (m = 4) at omega = 0.8: the plain FP64 RK4 solve, RKF45
+    beside it (its spread to the plain state sets the tie resolution), and the
+    PageRank-versus-quantum study."""
+    from paper_2003_04930_amd import study
+    n, w = 2048, 0.8
+    Pn = Q.Problem.from_graph(inputs.ba_digraph(n, 4, seed=0))
+    plain = Q.steady_state(Pn, w, DT, TOL, 400000)
+    rf = Q.steady_state(Pn, w, DT, TOL, 400000, integrator="rkf45")
+    err = float((rf.rho - plain.rho).abs().max())
+    log(f"n=2048 plain fp64: {plain.stats['seconds']:.2f} s, {plain.stats['steps']} steps")
+    return {"omega": w, "plain_fp64": {"seconds": plain.stats["seconds"],
+                                       "rk4_steps": plain.stats["steps"]},
+            "fp64_rkf45": {"seconds": rf.stats["seconds"], "steps": rf.stats["steps"],
+                           "max_abs_drho_vs_plain": err},
+            "study": study.hub_study(Q, Pn, plain.rho, 2 * err)}
+
+
+def config4_rows(Q, inputs, params, torch, np, mode):
+    """The batching workload: 256 family graphs (N uniform in [50, 922], half
+    ER with mean out-degree 4, half BA with m in 2..5) x 5 omegas = 1,280
+    systems to ||L|| < 1e-8.  "subset": FP64 RKF45 from the warm start over
+    all 1,280 systems (concurrent form) and the FP32 defect correction (FP32
+    steps, FP64 judge) over the first 32 graphs (160 systems) in both forms;
+    "full": the FP32 defect correction over all 1,280 in both forms too."""
+    items = []
+    for k in range(256):
+        Pk = Q.Problem.from_graph(inputs.batch_graph(k))
+        items += [(Pk, w) for w in inputs.BATCH_OMEGAS]
+    out = {"systems": len(items), "sum_n2": int(sum(P.n ** 2 for P, _ in items))}
+    runs = []
+    if params is not None:
+        runs.append(("rkf45_fp64_warm_concurrent", items, dict(prec="fp64", integrator="rkf45",
+                                                               mode="concurrent"), True))
+    sub = items if mode == "full" else items[:160]
+    runs.append(("mixed_fp32_concurrent", sub, dict(prec="fp32", mode="concurrent"), False))
+    runs.append(("mixed_fp32_persistent", sub, dict(prec="fp32", mode="persistent"), False))
+    for name, its, kw, warm in runs:
+        t0 = time.perf_counter()
+        rho0s = None
+        if warm:
+            from paper_2003_04930_amd import warmstart as W
+            rho0s = W.warm_rho0_batch(its, params)
+        rb = Q.batch_solve(its, tol=TOL, want_rank=True, rho0s=rho0s, **kw)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        st = [x["steps"] for x in rb.stats]
+        res = max(x["residual"] for x in rb.stats)
+        out[name] = {"systems": len(its), "seconds": secs, "solves_per_s": len(its) / secs,
+                     "steps_min_mean_max": [min(st), float(np.mean(st)), max(st)],
+                     "max_residual": res,
+                     "all_converged": all(x["converged"] == 1 for x in rb.stats)}
+        log(f"config4 {name}: {len(its)} systems in {secs:.1f} s ({len(its) / secs:.1f} solves/s)")
+        del rb
+    return out
 
 
 def main():
@@ -294,6 +376,8 @@ def main():
                     help="comma list of batched rows to time")
     ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "concurrent"],
                     help="how qpr_batch_solve runs the --batch-graphs systems")
+    ap.add_argument("--config4", default="subset", choices=["off", "subset", "full"],
+                    help="the 1,280-system batching workload (see config4_rows)")
     ap.add_argument("--precision-n", type=int, default=0,
                     help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
     ap.add_argument("--warm", default=WEIGHTS,
@@ -467,6 +551,15 @@ def main():
             extra["accelerated"] = accelerated(Q, W, P, params, results, value, torch, np)
             extra["target"] = target_rows(Q, W, P, params, results, value, torch, np)
 
+    if not args.no_rkf45:
+        # hub classes and degeneracy at N = 922, per omega (tie resolution:
+        # twice the spread between the RK4 and RKF45 steady states)
+        from paper_2003_04930_amd import study
+        tau = 2 * extra["fp64_rkf45"]["max_abs_drho_vs_rk4"]
+        extra["study_n922"] = {str(w): study.hub_study(Q, P, r.rho, tau)
+                               for w, r in zip(OMEGAS, results)}
+        extra["n2048"] = n2048_rows(Q, inputs, torch, np)
+
     if not args.no_4096:
         extra["n4096"] = n4096_rows(Q, inputs, params, torch, np, args)
         su = extra["n4096"]["stage_us"]
@@ -504,6 +597,9 @@ def main():
                 "product_frac": flops / (pm * 1e-3) / 1e12 / peak,
                 "speedup_vs_fp64": value / tm}
             log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
+
+    if args.config4 != "off":
+        extra["config4"] = config4_rows(Q, inputs, params, torch, np, args.config4)
 
     if args.batch_graphs:
         items = []
@@ -581,7 +677,7 @@ def main():
         "cpu_baseline": cpu,
         "extra": extra,
     }
-    print(json.dumps(line), flush=True)
+    print(json.dumps(line, default=_json_default), flush=True)
 
 
 if __name__ == "__main__":

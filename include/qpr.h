@@ -262,7 +262,7 @@ qpr_status qpr_rk4_step(const qpr_problem* P, double omega, double dt,
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation):
  * qpr_rk4_step with its workspace in a static device array the library
- * holds on every GPU it runs on (about 84 MB each, for the life of the
+ * holds on every GPU it runs on (73 MiB each, for the life of the
  * process) instead of a caller buffer.  Same arguments and results as
  * qpr_rk4_step without ws/ws_bytes; prec must be QPR_FP64 and n <= 1024.
  * Calls no allocating routine.  All calls on one GPU share that GPU's array:

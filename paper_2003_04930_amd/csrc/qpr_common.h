@@ -19,6 +19,14 @@ constexpr size_t kAlign = 256;    // every carved region starts on this boundary
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 inline int pad_n(int n) { return (n + kPad - 1) / kPad * kPad; }
+// Values of a Hermitian-packed tile-pair array (the accumulator, the Fehlberg
+// stage derivatives): a real and an imaginary 32 x 32 block per tile pair of
+// the upper triangle, (ld/32)(ld/32 + 1)/2 pairs -- ld^2 + 32 ld values, about
+// one plane instead of two.
+inline size_t packed_values(int ld) {
+  const size_t t = (size_t)ld / 32;
+  return t * (t + 1) / 2 * 2 * 32 * 32;
+}
 
 // Error reporting: sets this thread's last message and returns the status.
 qpr_status fail(qpr_status s, const char* fmt, ...);
@@ -116,7 +124,8 @@ struct Ws {
   double *yn_r = nullptr, *yn_i = nullptr;   // y_n (or the anchor delta in mixed mode)
   double *y1_r = nullptr, *y1_i = nullptr;   // stage states (ping)
   double *y2_r = nullptr, *y2_i = nullptr;   // stage states (pong)
-  double *acc_r = nullptr, *acc_i = nullptr; // RK4 accumulator
+  double *acc_r = nullptr, *acc_i = nullptr; // RK4 accumulator (Hermitian-packed by tile pair:
+                                             // acc_i = acc_r + 32 * 32)
   double *x_r = nullptr, *x_i = nullptr;     // X = H_off * Y (FP64 products)
   double *ra_r = nullptr, *ra_i = nullptr;   // mixed: FP64 anchor residual L(rho_a)
   double *an_r = nullptr, *an_i = nullptr;   // mixed: FP64 anchor rho_a
@@ -130,7 +139,8 @@ struct Ws {
   float *ra32_r = nullptr, *ra32_i = nullptr;
   uint16_t* sl = nullptr;                    // bf16 slices: [plane][slice][ld*ld]
   double *p_n = nullptr, *p_1 = nullptr, *p_2 = nullptr, *p_a = nullptr; // diagonals (n)
-  double *k_r[5] = {}, *k_i[5] = {};         // Fehlberg stage derivatives (FP64 only)
+  double *k_r[5] = {}, *k_i[5] = {};         // Fehlberg stage derivatives (FP64 only; packed
+                                             // as the accumulator)
   double *cand_r = nullptr, *cand_i = nullptr, *p_c = nullptr;  // Fehlberg candidate state
   double* partials = nullptr;                // per-workgroup partial sums
   int max_partials = 0;

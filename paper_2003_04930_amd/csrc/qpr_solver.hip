@@ -123,7 +123,8 @@ WsLayout ws_layout(int n, int prec, bool rkf) {
   L.yn = take(2 * pd);
   L.y1 = take(2 * pd);
   L.y2 = take(2 * pd);
-  L.acc = take(2 * pd);
+  const size_t pk = packed_values((int)ld) * 8;  // Hermitian-packed, by tile pair
+  L.acc = take(pk);
   L.x = take(2 * pd);
   if (prec != QPR_FP64) {
     L.ra = take(2 * pd);
@@ -134,7 +135,7 @@ WsLayout ws_layout(int n, int prec, bool rkf) {
   }
   L.pv = take(4 * ld * 8);
   if (prec == QPR_FP64 && rkf) {  // Fehlberg: K_1..K_5, candidate state and its diagonal
-    L.kf = take(10 * pd);
+    L.kf = take(5 * pk);
     L.cand = take(2 * pd);
     L.pc = take(ld * 8);
   }
@@ -169,7 +170,7 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
   w->y2_r = (double*)(b + L.y2);
   w->y2_i = w->y2_r + pl;
   w->acc_r = (double*)(b + L.acc);
-  w->acc_i = w->acc_r + pl;
+  w->acc_i = w->acc_r + 32 * 32;
   w->x_r = (double*)(b + L.x);
   w->x_i = w->x_r + pl;
   if (prec != QPR_FP64) {
@@ -189,8 +190,8 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
       w->d1_i = w->d1_r + pl;
       w->d2_r = (float*)(b + L.y2);
       w->d2_i = w->d2_r + pl;
-      w->dac_r = (float*)(b + L.acc);
-      w->dac_i = w->dac_r + pl;
+      w->dac_r = (float*)(b + L.acc);  // packed as the FP64 accumulator
+      w->dac_i = w->dac_r + 32 * 32;
       w->ra32_r = (float*)(b + L.x);
       w->ra32_i = w->ra32_r + pl;
     }
@@ -203,9 +204,10 @@ bool ws_carve(void* base, size_t bytes, int n, int prec, Ws* w, bool rkf) {
   w->p_a = pv + 3 * ld;
   if (prec == QPR_FP64 && rkf) {
     double* kf = (double*)(b + L.kf);
+    const size_t pk = packed_values((int)ld);
     for (int j = 0; j < 5; ++j) {
-      w->k_r[j] = kf + (2 * j) * pl;
-      w->k_i[j] = kf + (2 * j + 1) * pl;
+      w->k_r[j] = kf + j * pk;
+      w->k_i[j] = w->k_r[j] + 32 * 32;
     }
     w->cand_r = (double*)(b + L.cand);
     w->cand_i = w->cand_r + pl;
@@ -1099,7 +1101,7 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   QPR_HIP(launch_state_init(w.st, 0.0, 1ll << 60, CHK_PLAIN, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.y1_r, w.y1_i, w.p_1, s));
   QPR_HIP(launch_pad_in(rho, P->n, P->ld, w.yn_r, w.yn_i, w.p_n, s));
-  QPR_HIP(launch_fill(w.acc_r, 2 * (size_t)P->ld * P->ld * 8, s));
+  QPR_HIP(launch_fill(w.acc_r, packed_values(P->ld) * 8, s));
   if (xk != OP_F64) QPR_HIP(launch_to_lowp(xk, w.y1_r, w.y1_i, P->n, P->ld, w, s));
   // cfg = -2: time the sparse product (default variant) instead; cfg = -3 - v: sparse variant v;
   // v = nvar (the number of variants): the fused epilogue (no product launch);
@@ -1128,7 +1130,7 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   if (f32s) {  // FP32 state planes: the operand (as the FP32 copy) and zeros
     const size_t pl4 = 2 * (size_t)P->ld * P->ld * 4;
     QPR_HIP(launch_to_lowp(OP_F32, w.y1_r, w.y1_i, P->n, P->ld, w, s));
-    QPR_HIP(launch_fill(w.dac_r, pl4, s));
+    QPR_HIP(launch_fill(w.dac_r, packed_values(P->ld) * 4, s));
     QPR_HIP(launch_fill(w.ra32_r, pl4, s));
     QPR_HIP(hipMemcpyAsync(w.dn_r, w.lo_r, pl4, hipMemcpyDeviceToDevice, s));
     QPR_HIP(hipMemcpyAsync(w.d1_r, w.lo_r, pl4, hipMemcpyDeviceToDevice, s));
@@ -1249,9 +1251,9 @@ extern "C" qpr_status qpr_load_tuning(const char* cache_path) {
 // qpr_rk4_step_noalloc: qpr_rk4_step with its workspace in a file-scope
 // device array instead of a caller buffer, for callers that cannot allocate
 // (graph capture, tight serving loops).  FP64 products only, n <= 1024: the
-// workspace of an FP64 RK4 call at n = 1024 (y_n, two stage states, the
-// accumulator and X, 2 x 1024^2 doubles each, plus the diagonals, partials
-// and control block) is 83,952,128 bytes.  Every GPU the library runs on
+// workspace of an FP64 RK4 call at n = 1024 (y_n, two stage states and X,
+// 2 x 1024^2 doubles each, the tile-pair packed accumulator, the diagonals,
+// partials, slab lists and control block) is 75,834,112 bytes.  Every GPU the library runs on
 // holds one such array for the life of the process; calls on one GPU share
 // it, so calls that overlap on one GPU race.  Everything a call reads is
 // written earlier in the same call (the padded state planes by the pad-in
@@ -1260,7 +1262,7 @@ extern "C" qpr_status qpr_load_tuning(const char* cache_path) {
 // previous call, of whatever size, is read.
 namespace {
 constexpr int kNoAllocMaxN = 1024;
-constexpr size_t kScratchBytes = 84 * 1024 * 1024;
+constexpr size_t kScratchBytes = 73 * 1024 * 1024;
 constexpr int kMaxDevices = 64;
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 

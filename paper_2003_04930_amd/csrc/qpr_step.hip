@@ -273,9 +273,16 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   const bool need_yn = a.mode != EPI_RHS;
   const bool need_acc = a.mode == EPI_S2 || a.mode == EPI_S3 || a.mode == EPI_S4;
   double xa[EM], xb[EM], yr_[EM], yi_[EM], nr_[EM], ni_[EM], cr_[EM], ci_[EM], rr_[EM], ri_[EM];
+  // The accumulator and the Fehlberg stage derivatives are only ever touched
+  // on the evaluated tile (I, J): they are stored Hermitian-packed by tile
+  // pair -- pair t holds its 32 x 32 real block at [t][0] and imaginary block
+  // at [t][1] (accr / kr[j] point at [0][0], acci / ki[j] = that + 32 * 32),
+  // half the storage of two full planes, every access coalesced.
+  const size_t qbase = (size_t)tile * (2 * TE * TE) + tx;
   auto load_state = [&](int m) {  // Y_s, anchor residual, y_n, accumulator at element m
     const int ar = a0 + ty + ERS * m;
     const size_t o = (size_t)ar * ld + b;
+    const size_t q = qbase + (size_t)(ty + ERS * m) * TE;
     yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
     if (bin && ar < n) {
       yr_[m] = (double)s_ysr[o];
@@ -290,8 +297,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
       ni_[m] = (double)s_yni[o];
     }
     if (need_acc) {
-      cr_[m] = (double)s_accr[o];
-      ci_[m] = (double)s_acci[o];
+      cr_[m] = (double)s_accr[q];
+      ci_[m] = (double)s_acci[q];
     }
   };
 
@@ -387,6 +394,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     const int r = ty + ERS * m;
     const int ar = a0 + r;
     const size_t o = (size_t)ar * ld + b;
+    const size_t q = qbase + (size_t)r * TE;  // packed accumulator / stage derivatives
     double kr = 0.0, ki = 0.0;
     const bool inside = bin && ar < n;
     if (inside) {
@@ -412,15 +420,15 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         outi = ki;
         break;
       case EPI_S1:
-        s_accr[o] = (ST)kr;
-        s_acci[o] = (ST)ki;
+        s_accr[q] = (ST)kr;
+        s_acci[q] = (ST)ki;
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
       case EPI_S2:
       case EPI_S3:
-        s_accr[o] = (ST)(cr_[m] + 2.0 * kr);
-        s_acci[o] = (ST)(ci_[m] + 2.0 * ki);
+        s_accr[q] = (ST)(cr_[m] + 2.0 * kr);
+        s_acci[q] = (ST)(ci_[m] + 2.0 * ki);
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
@@ -434,7 +442,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
 #pragma unroll
         for (int j = 0; j < 5; ++j)
           if (j < fstage - 1) {
-            const double kjr = a.kr[j][o], kji = a.ki[j][o];
+            const double kjr = a.kr[j][q], kji = a.ki[j][q];
             sr += a.cf[j] * kjr;
             si += a.cf[j] * kji;
             er += a.ce[j] * kjr;
@@ -445,8 +453,8 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         er += a.ce[fstage - 1] * kr;
         ei += a.ce[fstage - 1] * ki;
         if (fstage < 6) {
-          a.kwr[o] = kr;
-          a.kwi[o] = ki;
+          a.kwr[q] = kr;
+          a.kwi[q] = ki;
         } else if (inside) {
           emax = fmax(emax, hstep * sqrt(er * er + ei * ei));
         }

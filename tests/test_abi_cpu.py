@@ -71,9 +71,11 @@ def test_size_queries_and_version():
     assert L.qpr_workspace_bytes(922, 0, 9) == 0        # unknown integrator
     assert L.qpr_workspace_bytes(922, 1, 1) == 0        # RKF45 is FP64 only
     w64 = L.qpr_workspace_bytes(922, 0, 0)
-    assert w64 >= 10 * 960 * 960 * 8          # y_n, two stage states, accumulator, X
+    packed = (30 * 31 // 2) * 2 * 32 * 32 * 8   # one Hermitian-packed tile-pair array
+    assert w64 >= 8 * 960 * 960 * 8 + packed   # y_n, two stage states, X; accumulator packed
+    assert w64 < 10 * 960 * 960 * 8
     rkf = L.qpr_workspace_bytes(922, 0, 1)
-    assert rkf >= w64 + 12 * 960 * 960 * 8    # + Fehlberg K_1..K_5 and the candidate
+    assert rkf >= w64 + 2 * 960 * 960 * 8 + 5 * packed   # + candidate, packed K_1..K_5
     assert L.qpr_workspace_bytes(922, 2, 0) >= 14 * 960 * 960 * 8
     assert b"gfx950" in L.qpr_version()
 
