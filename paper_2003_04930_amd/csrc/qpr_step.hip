@@ -236,7 +236,7 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const T* __rest
 // FP32 rounding of the FP64 result, and the mirrored tile stores the
 // conjugate of exactly that value (so the stored state stays bitwise
 // Hermitian).
-template <int XS>
+template <int XS, bool NT = false>
 __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs& a,
                                               DevState* __restrict__ st,
                                               double* __restrict__ partials, int tile) {
@@ -278,27 +278,42 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
   // pair -- pair t holds its 32 x 32 real block at [t][0] and imaginary block
   // at [t][1] (accr / kr[j] point at [0][0], acci / ki[j] = that + 32 * 32),
   // half the storage of two full planes, every access coalesced.
-  const size_t qbase = (size_t)tile * (2 * TE * TE) + tx;
+  // this thread's element m of the packed block sits at qoff + m * ERS * TE
+  const unsigned qoff = (unsigned)tile * (2 * TE * TE) + (unsigned)(ty * TE + tx);
+  // y_n, the anchor residual and the accumulator are read once per stage and
+  // touched again only at the next stage: on large problems (NT) they are
+  // loaded and the accumulator stored non-temporally, so they do not push the
+  // gathered rows of Y_s out of the caches (at N = 4096: 249 -> 235 us per
+  // FP32-state stage, 406 -> 397 us FP64; at N = 922, where the whole working
+  // set stays cached, it costs ~7 % and is not used)
+  auto ldt = [](const ST* p) -> double {
+    if constexpr (NT) return (double)__builtin_nontemporal_load(p);
+    else return (double)*p;
+  };
+  auto stt = [](ST* p, double v) {
+    if constexpr (NT) __builtin_nontemporal_store((ST)v, p);
+    else *p = (ST)v;
+  };
   auto load_state = [&](int m) {  // Y_s, anchor residual, y_n, accumulator at element m
     const int ar = a0 + ty + ERS * m;
     const size_t o = (size_t)ar * ld + b;
-    const size_t q = qbase + (size_t)(ty + ERS * m) * TE;
+    const unsigned q = qoff + (unsigned)(m * ERS * TE);
     yr_[m] = yi_[m] = nr_[m] = ni_[m] = cr_[m] = ci_[m] = rr_[m] = ri_[m] = 0.0;
     if (bin && ar < n) {
       yr_[m] = (double)s_ysr[o];
       yi_[m] = (double)s_ysi[o];
       if (a.rar) {
-        rr_[m] = (double)s_rar[o];
-        ri_[m] = (double)s_rai[o];
+        rr_[m] = ldt(&s_rar[o]);
+        ri_[m] = ldt(&s_rai[o]);
       }
     }
     if (need_yn) {
-      nr_[m] = (double)s_ynr[o];
-      ni_[m] = (double)s_yni[o];
+      nr_[m] = ldt(&s_ynr[o]);
+      ni_[m] = ldt(&s_yni[o]);
     }
     if (need_acc) {
-      cr_[m] = (double)s_accr[q];
-      ci_[m] = (double)s_acci[q];
+      cr_[m] = ldt(&s_accr[q]);
+      ci_[m] = ldt(&s_acci[q]);
     }
   };
 
@@ -394,7 +409,7 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
     const int r = ty + ERS * m;
     const int ar = a0 + r;
     const size_t o = (size_t)ar * ld + b;
-    const size_t q = qbase + (size_t)r * TE;  // packed accumulator / stage derivatives
+    const unsigned q = qoff + (unsigned)(m * ERS * TE);  // packed accumulator / derivatives
     double kr = 0.0, ki = 0.0;
     const bool inside = bin && ar < n;
     if (inside) {
@@ -420,15 +435,15 @@ __device__ __forceinline__ void epilogue_tile(const ProbView& pv, const EpiArgs&
         outi = ki;
         break;
       case EPI_S1:
-        s_accr[q] = (ST)kr;
-        s_acci[q] = (ST)ki;
+        stt(&s_accr[q], kr);
+        stt(&s_acci[q], ki);
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
       case EPI_S2:
       case EPI_S3:
-        s_accr[q] = (ST)(cr_[m] + 2.0 * kr);
-        s_acci[q] = (ST)(ci_[m] + 2.0 * ki);
+        stt(&s_accr[q], cr_[m] + 2.0 * kr);
+        stt(&s_acci[q], ci_[m] + 2.0 * ki);
         outr = nr_[m] + a.cdt * kr;
         outi = ni_[m] + a.cdt * ki;
         break;
@@ -644,11 +659,11 @@ __global__ void __launch_bounds__(FOLD_THREADS)
 
 // six waves per SIMD (<= 80 VGPRs, no spills): three 512-thread workgroups
 // per CU instead of two at the unconstrained 88 VGPRs
-template <int XS>
+template <int XS, bool NT = false>
 __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue(ProbView pv, EpiArgs a, DevState* __restrict__ st, double* __restrict__ partials) {
   if (st->stop || (a.gate && st->hold)) return;
-  epilogue_tile<XS>(pv, a, st, partials, blockIdx.x);
+  epilogue_tile<XS, NT>(pv, a, st, partials, blockIdx.x);
 }
 
 // The fused form (the sparse product gathered inside the tile), also at six
@@ -667,7 +682,7 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
 // X(I, J) half of the gathers reads Y's block J only, so that slice stays in
 // one L2 (fewer fetched bytes; at N = 4096 and above it costs more than it
 // saves).
-template <int XS>
+template <int XS, bool NT = false>
 __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue_fused(ProbView pv, EpiArgs a, DevState* __restrict__ st,
                      double* __restrict__ partials, FinishJob f, int xcd) {
@@ -678,7 +693,7 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
   }
   if (st->stop || (a.gate && st->hold)) return;
   const int nb = gridDim.x - extra, bid = blockIdx.x - extra;
-  epilogue_tile<XS>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
+  epilogue_tile<XS, NT>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
 }
 
 // Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
@@ -1284,23 +1299,36 @@ FinishJob finish_job(const ProbView& pv, const EpiArgs& a, const Ws& w) {
 
 hipError_t launch_epilogue(const ProbView& pv, const EpiArgs& a, const Ws& w, hipStream_t s,
                            bool finish, const FinishJob* carry) {
+  // non-temporal stage streams where the state outgrows the caches
+  const bool nt = pv.ld >= 4096;
   const int grid = tri_tiles(pv.ld / TE);
   if (grid * 3 > w.max_partials) return hipErrorInvalidValue;
   if (carry && a.xkind != XS_FUSED64 && a.xkind != XS_FUSED32 && a.xkind != XS_FUSED32S)
     return hipErrorInvalidValue;
-  if (a.xkind == XS_DENSE64)
-    k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else if (a.xkind == XS_DENSE32)
-    k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
-  else if (a.xkind == XS_SPARSE64)  // X already written by k_spmm: same epilogue
-    k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  if (a.xkind == XS_DENSE64 || a.xkind == XS_SPARSE64) {  // X written by the product
+    if (nt)
+      k_epilogue<XS_DENSE64, true><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+    else
+      k_epilogue<XS_DENSE64><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  } else if (a.xkind == XS_DENSE32) {
+    if (nt)
+      k_epilogue<XS_DENSE32, true><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+    else
+      k_epilogue<XS_DENSE32><<<grid, ETHREADS, 0, s>>>(pv, a, w.st, w.partials);
+  }
   else if (a.xkind == XS_FUSED64 || a.xkind == XS_FUSED32 || a.xkind == XS_FUSED32S) {
     const FinishJob f = carry ? *carry : FinishJob{};
     const int g = grid + (f.nb > 0 ? 1 : 0), xcd = pv.ld < 4096 ? 1 : 0;
-    if (a.xkind == XS_FUSED64)
+    if (a.xkind == XS_FUSED64 && nt)
+      k_epilogue_fused<XS_FUSED64, true><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
+    else if (a.xkind == XS_FUSED64)
       k_epilogue_fused<XS_FUSED64><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
+    else if (a.xkind == XS_FUSED32 && nt)
+      k_epilogue_fused<XS_FUSED32, true><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
     else if (a.xkind == XS_FUSED32)
       k_epilogue_fused<XS_FUSED32><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
+    else if (nt)
+      k_epilogue_fused<XS_FUSED32S, true><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
     else
       k_epilogue_fused<XS_FUSED32S><<<g, ETHREADS, 0, s>>>(pv, a, w.st, w.partials, f, xcd);
   } else {
