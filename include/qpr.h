@@ -370,6 +370,10 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *   stats   HOST qpr_stats[nsys] or NULL (per-system status in stats[k].status)
  *   tuned_cfg  HOST int32 or NULL: the tuned product configuration of the
  *           persistent form (-1: none, and always -1 in the concurrent form)
+ *   tune_cache  HOST path or NULL: a cache written by qpr_autotune, loaded
+ *           (qpr_load_tuning) before the solve, so its dense tiles, sparse
+ *           variants and stage forms are the ones the batch uses; NULL keeps
+ *           the process's current tuning
  * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP, and after a
  * full run QPR_E_NONFINITE / QPR_E_NOT_CONVERGED if any system failed.
  * Synchronises once per chunk.
@@ -378,8 +382,9 @@ qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* probs,
                            const double* omegas, double dt, double tol,
                            int64_t max_steps, int32_t prec, double* const* rhos,
                            int32_t* const* ranks, qpr_stats* stats,
-                           const qpr_opts* opts, int32_t* tuned_cfg, void* ws,
-                           size_t ws_bytes, qpr_stream_t stream);
+                           const qpr_opts* opts, int32_t* tuned_cfg,
+                           const char* tune_cache, void* ws, size_t ws_bytes,
+                           qpr_stream_t stream);
 
 /*
  * Rank nodes by descending p (device, n doubles), ties by ascending index,
@@ -475,6 +480,11 @@ qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32_t prec,
  * P's padded size (`reps` launches each, HIP events on `stream`), make the
  * fastest the default for that (precision, size) in this process and, if
  * cache_path is not NULL, append "prec ld cfg microseconds name" to it.
+ * With QPR_FP64 it also times every sparse-product variant (the fastest
+ * becomes the default for this size: line "10 ld variant us name") and the
+ * two forms of a sparse RK4 stage, product + epilogue against the fused
+ * epilogue (what QPR_PRODUCT_AUTO runs for a lone FP64 solve of this size:
+ * line "11 ld 0|1 us-per-stage name").
  *   best_cfg  host int32 or NULL;  us_out  host double[qpr_product_configs(prec)]
  *             or NULL (-1 for configurations whose tile does not divide ld)
  * Errors: QPR_E_ARG, QPR_E_WORKSPACE, QPR_E_HIP.  Synchronises.

@@ -195,8 +195,9 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
                                       const double* omegas, double dt, double tol,
                                       int64_t max_steps, int32_t prec, double* const* rhos,
                                       int32_t* const* ranks, qpr_stats* stats,
-                                      const qpr_opts* opts, int32_t* tuned_cfg, void* ws,
-                                      size_t ws_bytes_, qpr_stream_t stream) {
+                                      const qpr_opts* opts, int32_t* tuned_cfg,
+                                      const char* tune_cache, void* ws, size_t ws_bytes_,
+                                      qpr_stream_t stream) {
   const auto t0 = std::chrono::steady_clock::now();
   clear_error();
   if (nsys < 1) return fail(QPR_E_ARG, "nsys must be >= 1");
@@ -206,6 +207,11 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   if (!(tol > 0.0)) return fail(QPR_E_ARG, "tol must be positive");
   if (max_steps < 0) return fail(QPR_E_ARG, "max_steps must be >= 0");
   if (!ws || ((uintptr_t)ws) % kAlign) return fail(QPR_E_ARG, "workspace must be 256-byte aligned");
+  if (tune_cache) {
+    const qpr_status ts = qpr_load_tuning(tune_cache);
+    if (ts != QPR_OK) return ts;  // its message names the cache
+    clear_error();
+  }
   qpr_opts o{};
   o.use_graph = 1;
   o.renorm = 1;

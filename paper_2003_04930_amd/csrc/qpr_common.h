@@ -316,6 +316,11 @@ hipError_t launch_spmm_batch(const BatchEpi* args, const int2* items, const int*
 hipError_t launch_spmm_f32_batch(const BatchEpi* args, const int2* items, const int* nitems,
                                  int grid, hipStream_t s);
 
+// Tuned choices beside the dense tiles (qpr_autotune, qpr_load_tuning), per
+// padded size, looked up exactly: the sparse-product variant, and whether
+// a lone FP64 solve takes the fused epilogue (1) or product + epilogue (0).
+constexpr int kTuneSparseVariant = 10, kTuneFusedStage = 11;
+bool tuned_exact(int kind, int ld, int* cfg);
 int gemm_num_cfgs(int kind);
 const char* gemm_cfg_name(int kind, int cfg);
 int gemm_default_cfg(int kind, int n);

@@ -592,6 +592,16 @@ void gemm_set_tuned(int kind, int ld, int cfg) {
   g_tune.push_back({kind, ld, cfg});
 }
 
+bool tuned_exact(int kind, int ld, int* cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (e.kind == kind && e.ld == ld) {
+      *cfg = e.cfg;
+      return true;
+    }
+  return false;
+}
+
 int gemm_default_cfg(int kind, int n) {
   const int ld = pad_n(n);
   std::lock_guard<std::mutex> lk(g_tune_mu);

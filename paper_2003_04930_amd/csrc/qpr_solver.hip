@@ -64,7 +64,10 @@ static int x_source(const qpr_problem* P, int product, int xk) {
                                                                                   : XS_DENSE32;
   if (product == QPR_PRODUCT_FUSED) return XS_FUSED64;
   if (!sparse) return XS_DENSE64;
-  return product == QPR_PRODUCT_AUTO && P->ld >= 4096 ? XS_FUSED64 : XS_SPARSE64;
+  if (product != QPR_PRODUCT_AUTO) return XS_SPARSE64;
+  int fused;  // the autotuner's choice for this padded size, else the measured rule
+  if (tuned_exact(kTuneFusedStage, P->ld, &fused)) return fused ? XS_FUSED64 : XS_SPARSE64;
+  return P->ld >= 4096 ? XS_FUSED64 : XS_SPARSE64;
 }
 
 // The problem view with the sparse-product variant the options ask for.
@@ -1218,10 +1221,69 @@ extern "C" qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t r
   if (best < 0) return fail(QPR_E_HIP, "no product configuration ran");
   gemm_set_tuned(xk, P->ld, best);
   if (best_cfg) *best_cfg = best;
+  // FP64: also the sparse-product variant and the form of a lone solve's
+  // sparse stage (product + epilogue, or the fused epilogue), timed as RK4
+  // steps (the four stage epilogues, finishing steps not included)
+  int sv = -1, fused = -1;
+  double sv_us = 0.0, stage_us[2] = {0.0, 0.0};
+  if (xk == OP_F64) {
+    const ProbView pv = view_of(P);
+    auto time_us = [&](const std::function<hipError_t()>& f, double* us) -> qpr_status {
+      QPR_HIP(f());
+      QPR_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) QPR_HIP(f());
+      QPR_HIP(hipEventRecord(e1, s));
+      QPR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      *us = 1e3 * (double)ms / reps;
+      return QPR_OK;
+    };
+    QPR_HIP(launch_fill(w.acc_r, packed_values(P->ld) * 8, s));
+    QPR_HIP(launch_fill(w.yn_r, 2 * plane * 8, s));
+    double best_v = 1e300;
+    for (int v = 0; v < spmm_num_variants(); ++v) {
+      double us = 0.0;
+      st = time_us([&]() { return launch_spmm(pv, w.y1_r, w.y1_i, w.x_r, w.x_i, w.st, 0, s, v); },
+                   &us);
+      if (st != QPR_OK) return st;
+      if (us < best_v) {
+        best_v = us;
+        sv = v;
+      }
+    }
+    sv_us = best_v;
+    for (int form = 0; form < 2; ++form) {
+      const int xs = form ? XS_FUSED64 : XS_SPARSE64;
+      st = time_us(
+          [&]() -> hipError_t {
+            for (int k = 0; k < 4; ++k) {
+              const EpiArgs a = rk4_stage_args(w, k, 0.5, 0.01, OP_F64, xs, CHK_NONE, 0, false);
+              if (!form) {
+                hipError_t e = launch_spmm(pv, a.ysr, a.ysi, w.x_r, w.x_i, w.st, 0, s, sv);
+                if (e != hipSuccess) return e;
+              }
+              hipError_t e = launch_epilogue(pv, a, w, s, false);
+              if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+          },
+          &stage_us[form]);
+      if (st != QPR_OK) return st;
+    }
+    fused = stage_us[1] < stage_us[0] ? 1 : 0;
+    gemm_set_tuned(kTuneSparseVariant, P->ld, sv);
+    gemm_set_tuned(kTuneFusedStage, P->ld, fused);
+  }
   if (cache_path && cache_path[0]) {
     FILE* f = fopen(cache_path, "a");
     if (!f) return fail(QPR_E_ARG, "cannot open tuning cache %s", cache_path);
     fprintf(f, "%d %d %d %.3f %s\n", prec, P->ld, best, best_us, gemm_cfg_name(xk, best));
+    if (sv >= 0) {
+      fprintf(f, "%d %d %d %.3f %s\n", kTuneSparseVariant, P->ld, sv, sv_us, spmm_variant_name(sv));
+      fprintf(f, "%d %d %d %.3f %s\n", kTuneFusedStage, P->ld, fused, stage_us[fused] / 4.0,
+              fused ? "fused_epilogue" : "product+epilogue");
+    }
     fclose(f);
   }
   return QPR_OK;
@@ -1237,8 +1299,19 @@ extern "C" qpr_status qpr_load_tuning(const char* cache_path) {
   char name[128];
   int loaded = 0;
   while (fscanf(f, "%d %d %d %lf %127s", &prec, &ld, &cfg, &us, name) == 5) {
+    if (ld <= 0 || ld % kPad != 0) continue;
+    if (prec == kTuneSparseVariant || prec == kTuneFusedStage) {
+      const bool ok = prec == kTuneSparseVariant ? cfg >= 0 && cfg < spmm_num_variants()
+                                                 : cfg == 0 || cfg == 1;
+      if (ok) {
+        gemm_set_tuned(prec, ld, cfg);
+        ++loaded;
+      }
+      continue;
+    }
+    if (prec != QPR_FP64 && prec != QPR_FP32 && prec != QPR_BF16X3) continue;
     const int xk = op_kind(prec);
-    if (cfg >= 0 && cfg < gemm_num_cfgs(xk) && ld > 0 && ld % kPad == 0) {
+    if (cfg >= 0 && cfg < gemm_num_cfgs(xk)) {
       gemm_set_tuned(xk, ld, cfg);  // later lines win
       ++loaded;
     }

@@ -1362,6 +1362,8 @@ const char* spmm_variant_name(int v) { return v >= 0 && v < kNumSpmm ? kSpmm[v].
 // Default by size (measured, BA graphs): the row-major kernel up to N ~ 1000,
 // 128-column chunks where ld is a multiple of 128 and the matrix is large.
 int spmm_default_variant(const ProbView& pv) {
+  int v;
+  if (tuned_exact(kTuneSparseVariant, pv.ld, &v) && v >= 0 && v < kNumSpmm) return v;
   return pv.ld % 128 == 0 && pv.n >= 1536 ? 2 : 4;
 }
 

@@ -134,7 +134,7 @@ def lib():
         "qpr_load_tuning": (i32, [C.c_char_p]),
         "qpr_batch_workspace_bytes": (sz, [i32, vp, i32, C.POINTER(qpr_opts)]),
         "qpr_batch_solve": (i32, [i32, vp, vp, dbl, dbl, i64, i32, vp, vp, C.POINTER(qpr_stats),
-                                  C.POINTER(qpr_opts), C.POINTER(i32), vp, sz, vp]),
+                                  C.POINTER(qpr_opts), C.POINTER(i32), C.c_char_p, vp, sz, vp]),
         "qpr_product_config_name": (C.c_char_p, [i32, i32]),
         "qpr_sparse_variants": (i32, []),
         "qpr_sparse_variant_name": (C.c_char_p, [i32]),
@@ -608,7 +608,7 @@ class BatchResult:
 def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=None,
                 want_rank=True, chunk=0, use_graph=True, gemm_cfg=-1, product="auto",
                 allow_not_converged=False, integrator="rk4", step_tol=1e-4, dt_max=0.0,
-                mode="auto", workers=0, delta_state="auto"):
+                mode="auto", workers=0, delta_state="auto", tune_cache=None):
     """Solve [(Problem, omega), ...] together with qpr_batch_solve (mode "auto" or
     "concurrent": a pool of worker streams; "persistent": shared launches).
     chunk 0 takes the library's default for the mode."""
@@ -641,7 +641,8 @@ def batch_solve(items, dt=0.01, tol=1e-8, max_steps=400000, prec="fp64", rho0s=N
     t0 = _time.perf_counter()
     status = lib().qpr_batch_solve(nsys, probs, omegas, float(dt), float(tol), int(max_steps),
                                    PREC[prec], rho_ptrs, rank_ptrs, stats, C.byref(op),
-                                   C.byref(tuned), C.c_void_p(base), nbytes, _stream())
+                                   C.byref(tuned), tune_cache.encode() if tune_cache else None,
+                                   C.c_void_p(base), nbytes, _stream())
     secs = _time.perf_counter() - t0
     _check(status, allow=(QPR_E_NOT_CONVERGED,) if allow_not_converged else ())
     return BatchResult(rhos, ranks, [s.as_dict() for s in stats], status, int(tuned.value), secs)

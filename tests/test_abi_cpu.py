@@ -171,7 +171,7 @@ def test_batch_workspace_query_and_mode_check():
     op.batch_mode = 5
     st = L.qpr_batch_solve(1, (C.c_void_p * 1)(C.addressof(P)), (C.c_double * 1)(0.5), 0.01,
                            1e-8, 10, 0, (C.c_void_p * 1)(256), None, None, C.byref(op), None,
-                           C.c_void_p(256), 1 << 20, None)
+                           None, C.c_void_p(256), 1 << 20, None)
     assert st == qpr.QPR_E_ARG and "batch_mode" in L.qpr_last_error().decode()
 
 
@@ -180,3 +180,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(qpr, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(qpr.QprError):
         qpr.lib()
+
+
+def test_load_tuning_parses_every_entry_kind(tmp_path):
+    """Dense tiles (precision codes 0-2), the sparse-product variant (10) and
+    the stage form (11) load; malformed or out-of-range lines are skipped and
+    a cache with none left is an error."""
+    L = _lib()
+    good = tmp_path / "tune.txt"
+    good.write_text("0 960 1 139.2 f64_32x32_w16x16_k16\n"
+                    "10 960 4 11.9 row128\n"
+                    "11 960 0 24.4 product+epilogue\n"
+                    "11 4096 1 401.0 fused_epilogue\n")
+    assert L.qpr_load_tuning(str(good).encode()) == qpr.QPR_OK
+    bad = tmp_path / "bad.txt"
+    bad.write_text("10 960 99 1.0 none\n11 960 7 1.0 none\n3 960 0 1.0 none\n0 100 0 1.0 odd\n")
+    assert L.qpr_load_tuning(str(bad).encode()) == qpr.QPR_E_ARG
+    assert L.qpr_load_tuning(str(tmp_path / "absent.txt").encode()) == qpr.QPR_E_ARG

@@ -158,5 +158,24 @@ def test_concurrent_batch_mixed_sizes_and_errors(Q):
     pa = (C.POINTER(Q.qpr_problem) * 1)(C.pointer(probs[0].p))
     st = L.qpr_batch_solve(1, pa, (C.c_double * 1)(0.5), 0.01, 1e-8, 1000, 0,
                            (C.c_void_p * 1)(out.rhos[0].data_ptr()), None, None, C.byref(op),
-                           None, C.c_void_p(256), 1 << 20, None)
+                           None, None, C.c_void_p(256), 1 << 20, None)
     assert st == Q.QPR_E_ARG and "batch_mode" in L.qpr_last_error().decode()
+
+
+def test_autotune_sparse_choices_and_tune_cache(Q, tmp_path):
+    """The autotuner also picks the sparse-product variant and the stage form
+    for the size and writes them to the cache; every variant and form gives
+    the same sums, so a solve after tuning is bitwise the one before, and
+    qpr_batch_solve takes the cache through its tune_cache argument."""
+    P = Q.Problem.from_graph(inputs.ba_digraph(300, 3, seed=8))
+    before = Q.steady_state(P, 0.6, 0.01, 1e-9, 400000)
+    cache = tmp_path / "tune.txt"
+    Q.autotune(P, "fp64", reps=3, cache_path=str(cache))
+    kinds = [int(line.split()[0]) for line in cache.read_text().splitlines()]
+    assert kinds == [0, 10, 11]
+    after = Q.steady_state(P, 0.6, 0.01, 1e-9, 400000)
+    assert torch.equal(before.rho, after.rho) and before.stats["steps"] == after.stats["steps"]
+    out = Q.batch_solve([(P, 0.6)], tol=1e-9, tune_cache=str(cache))
+    assert torch.equal(out.rhos[0], before.rho)
+    with pytest.raises(Q.QprError):
+        Q.batch_solve([(P, 0.6)], tol=1e-9, tune_cache=str(tmp_path / "absent.txt"))

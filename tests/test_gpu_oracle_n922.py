@@ -1,0 +1,106 @@
+"""The N = 922 workload against the oracle's own steady state.
+
+tests/golden/ss_ba922_diag.txt holds the populations Re rho_aa of the
+oracle's RK4 run to ||L||_F < 1e-12 at omega = 0.2, 0.5, 0.8 (written by
+make_ss_ba922.py from oracle/ only).  Every solver form -- plain FP64 RK4,
+the paper's RKF45, and the spec form (qpr_batch_solve with the FP32
+defect correction from the learned warm start) -- stopped at 1e-8 must
+match it within the 1e-6 bound of the mixed solves (observed ~1e-8), have
+its residual confirmed by the oracle's right-hand side, and rank the nodes
+as the oracle does on every pair whose oracle gap exceeds twice the measured
+population error (closer pairs are tie classes: both orders are correct).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_04930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OMEGAS = (0.2, 0.5, 0.8)
+WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2003_04930_amd", "weights",
+                       "mpnn_warmstart.npy")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2003_04930_amd import qpr
+    qpr.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return qpr
+
+
+@pytest.fixture(scope="module")
+def golden():
+    rows = []
+    with open(os.path.join(HERE, "golden", "ss_ba922_diag.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(x) for x in line.split()[1:]])
+    p = np.array(rows)
+    assert p.shape == (922, 3)
+    return {w: p[:, k] for k, w in enumerate(OMEGAS)}
+
+
+@pytest.fixture(scope="module")
+def workload(Q):
+    g = inputs.ba_digraph(922, 3, seed=0)
+    return Q.Problem.from_graph(g), O.problem_ref(g.n, g.src, g.dst)
+
+
+def order_violations(p_ref, rank, tau):
+    """Pairs with p_ref gap > tau that `rank` orders the other way."""
+    pos = np.empty(p_ref.size, dtype=np.int64)
+    pos[rank] = np.arange(p_ref.size)
+    order = np.argsort(-p_ref, kind="stable")
+    ps = p_ref[order]
+    lo = np.searchsorted(-ps, -ps + tau, side="right")
+    suffix_min = np.minimum.accumulate(pos[order][::-1])[::-1]
+    return int(sum(1 for i in range(ps.size)
+                   if lo[i] < ps.size and suffix_min[lo[i]] < pos[order[i]]))
+
+
+def check_against_oracle(Q, R, golden, omega, rho_planar, rank):
+    rho = Q.to_complex(rho_planar)
+    res = np.sqrt(np.sum(np.abs(O.rhs_ref(rho, R.H_sparse, R.G, R.d, omega)) ** 2))
+    assert res < 1e-8 * (1 + 1e-6), res
+    assert np.array_equal(rho, rho.conj().T)
+    p = np.diag(rho).real
+    err = float(np.max(np.abs(p - golden[omega])))
+    assert err < 1e-6, err
+    assert order_violations(golden[omega], rank.cpu().numpy(), 2 * err + 1e-15) == 0
+    return err
+
+
+@pytest.mark.parametrize("omega", OMEGAS)
+def test_plain_fp64_matches_oracle_steady_state(Q, golden, workload, omega):
+    P, R = workload
+    out = Q.steady_state(P, omega, 0.01, 1e-8, 400000)
+    err = check_against_oracle(Q, R, golden, omega, out.rho, out.rank)
+    assert err < 1e-7
+
+
+def test_north_star_form_matches_oracle(Q, golden, workload):
+    """qpr_batch_solve, FP32 steps with the FP64 fold and judge, from the
+    learned warm start, the three omegas together."""
+    from paper_2003_04930_amd import warmstart as W
+    P, R = workload
+    params = W.load(WEIGHTS)
+    items = [(P, w) for w in OMEGAS]
+    out = Q.batch_solve(items, tol=1e-8, prec="fp32", rho0s=W.warm_rho0_batch(items, params))
+    for k, w in enumerate(OMEGAS):
+        assert out.stats[k]["converged"] == 1
+        check_against_oracle(Q, R, golden, w, out.rhos[k], out.ranks[k])
+
+
+@pytest.mark.parametrize("omega", OMEGAS)
+def test_rkf45_matches_oracle_steady_state(Q, golden, workload, omega):
+    P, R = workload
+    out = Q.steady_state(P, omega, 0.01, 1e-8, 400000, integrator="rkf45")
+    check_against_oracle(Q, R, golden, omega, out.rho, out.rank)
