@@ -90,7 +90,9 @@ typedef struct {
   double alpha;         /* damping of the Google matrix                       */
   int32_t teleport;     /* qpr_teleport                                       */
   int32_t hdiag;        /* qpr_hdiag                                          */
-  double h_lo, h_hi;    /* Gershgorin interval containing the spectrum of H   */
+  double h_lo, h_hi;    /* interval containing the spectrum of H: Gershgorin's,
+                           narrowed to [-b, b] by a Collatz-Wielandt bound b on
+                           its spectral radius (the RK4 stability check uses it) */
   double h_norm;        /* spectral radius of H, power-iteration estimate     */
   int32_t pagerank_iters; /* power iterations used for `pagerank`             */
   int32_t reserved;

@@ -315,6 +315,31 @@ __global__ void __launch_bounds__(1024) k_spectral(int n, const int* __restrict_
     if (!(nrm2 > 0.0)) break;
   }
   if (t == 0) sm->h_norm = best;
+  // Rigorous upper bound on the spectral radius (Collatz-Wielandt): for any
+  // positive u, rho(H) <= rho(|H|) <= max_i (|H| u)_i / u_i.  With u the
+  // magnitude of the last iterate (near the Perron vector of |H| on the
+  // dominant component), lifted by 1e-3 of its maximum so that it is positive
+  // everywhere, the bound is close to rho(H).  The Gershgorin interval of the
+  // spectrum (2 x the largest degree wide, loose on graphs with hubs) is
+  // intersected with [-bound, bound]; the RK4 stability check uses it.
+  double xm = 0.0;
+  for (int i = t; i < n; i += 1024) xm = fmax(xm, fabs(x[i]));
+  xm = block_max(xm, red, 1024 / 64);
+  if (xm > 0.0 && isfinite(xm)) {
+    const double lift = 1e-3 * xm;
+    double bnd = 0.0;
+    for (int i = t; i < n; i += 1024) {
+      const double ui = fabs(x[i]) + lift;
+      double z = fabs(hd[i]) * ui;
+      for (int e = h_ptr[i]; e < h_ptr[i + 1]; ++e) z += fabs(x[h_idx[e]]) + lift;
+      bnd = fmax(bnd, z / ui);
+    }
+    bnd = block_max(bnd, red, 1024 / 64);
+    if (t == 0 && isfinite(bnd)) {
+      sm->h_lo = fmax(sm->h_lo, -bnd);
+      sm->h_hi = fmin(sm->h_hi, bnd);
+    }
+  }
 }
 
 }  // namespace

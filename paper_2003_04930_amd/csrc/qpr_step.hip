@@ -204,11 +204,23 @@ __device__ __forceinline__ void fused_gather(const ProbView& pv, const T* __rest
       double* acc = v[q];
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] = 0.0 + (f0 + k < f1 ? acc[k] : 0.0);
-      for (int e = f0 + 8; e < f1; e += 8) {  // rows with more than eight neighbours
+      // rows with more than eight neighbours: groups of eight, the next
+      // group's indices (wave-uniform, scalar loads) fetched while the
+      // current group's rows are in flight, so a long row costs one memory
+      // round trip per group rather than two
+      int nx[8];
+      if (f0 + 8 < f1) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nx[k] = pv.h_idx[min(f0 + 8 + k, f1 - 1)];
+      }
+      for (int e = f0 + 8; e < f1; e += 8) {
         double u[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          u[k] = (double)base[q][(size_t)pv.h_idx[min(e + k, f1 - 1)] * ld];
+        for (int k = 0; k < 8; ++k) u[k] = (double)base[q][(size_t)nx[k] * ld];
+        if (e + 8 < f1) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) nx[k] = pv.h_idx[min(e + 8 + k, f1 - 1)];
+        }
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] += e + k < f1 ? u[k] : 0.0;
       }
@@ -756,15 +768,26 @@ __device__ __forceinline__ void gather_rows(const int* __restrict__ h_idx, int e
 #pragma unroll
     for (int q = 0; q < S; ++q) acc[k][q] = 0.0;
   int e = e0;
+  // the next full group's indices are fetched while the current group's rows
+  // are in flight (one memory round trip per group, not two)
+  int nx[8];
+  if (e + 8 <= e1) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nx[k] = h_idx[e + k];
+  }
   for (; e + 8 <= e1; e += 8) {
     size_t off[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) off[k] = (size_t)h_idx[e + k] * ld;
+    for (int k = 0; k < 8; ++k) off[k] = (size_t)nx[k] * ld;
     double v[8][S];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll
       for (int q = 0; q < S; ++q) v[k][q] = (double)base[q][off[k]];
+    if (e + 16 <= e1) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) nx[k] = h_idx[e + 8 + k];
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll

@@ -137,12 +137,11 @@ def main():
         row.update({"max_abs_drho_warm_vs_identity": drho, "rankings_identical": same_rank})
         summary[integ] = row
         del res
-    summary["seconds"] = time.perf_counter() - t0
-    line = json.dumps(summary)
-    if args.out:
-        with open(args.out, "w") as fh:
-            fh.write(line + "\n")
-    print(line, flush=True)
+        summary["seconds"] = time.perf_counter() - t0
+        if args.out:  # after each integrator, so a later failure keeps this one
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps(summary) + "\n")
+    print(json.dumps(summary), flush=True)
 
 
 if __name__ == "__main__":

@@ -231,12 +231,21 @@ def test_rkf45_steady_state_matches_rk4_fixed_point(Q):
 
 
 def test_spectral_radius_estimate(Q):
-    for g in (GRAPHS["ba300"](), inputs.ba_digraph(922, 3, seed=0)):
+    """h_norm is the power-iteration estimate of rho(H) (a lower bound);
+    [h_lo, h_hi] must contain the whole spectrum (rigorous), and with the
+    Collatz-Wielandt bound it is close to +-rho(H) even on hub graphs whose
+    Gershgorin interval is twice the largest degree wide."""
+    for g in (GRAPHS["ba300"](), inputs.ba_digraph(922, 3, seed=0), _hub_and_isolated(),
+              inputs.er_digraph(200, 0.01, seed=5)):
         for hdiag in ("zero", "paper"):
             P = Q.Problem.from_graph(g, hdiag=hdiag)
             R = oracle_problem(g, hdiag=hdiag)
-            rho = np.max(np.abs(np.linalg.eigvalsh(R.H)))
+            ev = np.linalg.eigvalsh(R.H)
+            rho = np.max(np.abs(ev))
             assert 0.97 * rho <= P.p.h_norm <= rho * (1 + 1e-9)
+            assert P.p.h_lo <= ev[0] + 1e-12 and ev[-1] <= P.p.h_hi + 1e-12
+            if g.n >= 300:      # connected scale-free graphs: the bound is tight
+                assert P.p.h_hi - P.p.h_lo <= 2.2 * rho
 
 
 # ---------------------------------------------------------------- ranking
