@@ -50,7 +50,7 @@ __all__ = [
     "hamiltonian", "ProblemRef", "problem_ref", "jump_operators",
     "lindblad_rhs_literal", "rhs_ref", "liouvillian_bruteforce", "vec",
     "unvec", "rk4_step_ref", "rk4_ref", "steady_ref", "pagerank_power",
-    "rank_ref", "hub_classes_ref", "rkf45_ref", "FEHLBERG",
+    "rank_ref", "hub_classes_ref", "rkf45_ref", "FEHLBERG", "steady_null_ref",
 ]
 
 
@@ -254,6 +254,35 @@ def steady_ref(y0, f, h, tol, max_steps, renorm=False):
         if renorm:
             y = y / np.trace(y).real
     raise RuntimeError(f"not converged after {max_steps} steps (residual {res:.3e})")
+
+
+def steady_null_ref(f, n, tol=1e-13, restart=60, maxiter=2000):
+    """The steady state by its definition, without time stepping: the unique
+    trace-one rho with L(rho) = 0 (the null vector of the Liouvillian of
+    Eq. (2), here applied matrix-free through f = L).
+
+    Write rho = I/n + X with tr X = 0.  L maps every matrix to a traceless one,
+    so L(X) = -L(I/n) has its right-hand side in the traceless subspace, on
+    which L is invertible when the steady state is unique; GMRES started from
+    X = 0 (scipy, no preconditioner) stays in that subspace.  Returns
+    (rho, ||L(rho)||_F, iterations).
+    """
+    import scipy.sparse.linalg as spla
+    eye = np.eye(n, dtype=np.complex128) / n
+    b = -np.asarray(f(eye)).ravel()
+    op = spla.LinearOperator((n * n, n * n), dtype=np.complex128,
+                             matvec=lambda x: np.asarray(f(x.reshape(n, n))).ravel())
+    its = [0]
+
+    def count(_):
+        its[0] += 1
+    x, info = spla.gmres(op, b, rtol=tol, atol=0.0, restart=restart, maxiter=maxiter,
+                         callback=count, callback_type="pr_norm")
+    if info != 0:
+        raise RuntimeError(f"GMRES did not converge (info={info})")
+    rho = eye + x.reshape(n, n)
+    res = float(np.sqrt(np.sum(np.abs(f(rho)) ** 2)))
+    return rho, res, its[0]
 
 
 # ---------------------------------------------------------- classical + ranks

@@ -10,6 +10,8 @@ Calls only the oracle and the seeded graph generator:
 
 With omegas given, each is written to ss_ba922_diag.<omega>.part; without,
 the parts are merged into ss_ba922_diag.txt.  About an hour of CPU per omega.
+With --check, the omega = 0.8 column is compared with the GMRES null vector
+of L (the oracle's time-stepping-free steady state).
 """
 import os
 import sys
@@ -34,7 +36,29 @@ def solve(omega):
     return np.diag(y).real.copy(), steps, res, float(np.trace(y).real)
 
 
+def cross_check(omega=0.8):
+    """The stored populations against the oracle's other route to the steady
+    state, the GMRES null vector of L (no time stepping)."""
+    g = inputs.ba_digraph(922, 3, seed=0)
+    R = O.problem_ref(g.n, g.src, g.dst)
+    f = lambda r: O.rhs_ref(r, R.H_sparse, R.G, R.d, omega)
+    rho, res, its = O.steady_null_ref(f, g.n, tol=1e-12, restart=60, maxiter=400)
+    col = OMEGAS.index(omega)
+    stored = []
+    with open(os.path.join(HERE, "ss_ba922_diag.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                stored.append(float(line.split()[1 + col]))
+    d = float(np.max(np.abs(np.diag(rho).real - np.array(stored))))
+    print(f"omega {omega}: GMRES null vector ({its} iterations, residual {res:.2e}) "
+          f"against the stored populations: max |dp| = {d:.2e}")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--check":
+        cross_check()
+        return
     if len(sys.argv) > 1:
         for w in map(float, sys.argv[1:]):
             p, steps, res, tr = solve(w)

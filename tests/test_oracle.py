@@ -439,3 +439,26 @@ def test_rkf45_tracks_matrix_exponential():
     y, t, acc, rej = O.rkf45_ref(rho0, lambda r: O.rhs_ref(r, P.H, P.G, P.d, omega), 0.01, 1e-9, t_end=T)
     assert abs(t - T) < 1e-12 and acc > 2
     assert np.max(np.abs(y - exact)) < 1e-7
+
+
+def test_null_vector_steady_state_agrees_with_brute_force_and_rk4():
+    """Two independent routes to the steady state of the oracle: the GMRES
+    null vector of L (no time stepping) against the SVD null vector of the
+    brute-force Kronecker Liouvillian (N = 6) and against RK4 run to 1e-13
+    (N = 40, both H diagonals)."""
+    P = small_problem(6, seed=11)
+    f = lambda r: O.rhs_ref(r, P.H, P.G, P.d, 0.45)
+    rho, res, _ = O.steady_null_ref(f, 6)
+    Lv = O.liouvillian_bruteforce(P.H, P.G, 0.45)
+    _, _, vh = np.linalg.svd(Lv)
+    v = O.unvec(vh[-1].conj(), 6)
+    v = v / np.trace(v)
+    assert res < 1e-12 and np.max(np.abs(rho - v)) < 1e-12
+    for hdiag in ("zero", "paper"):
+        g = inputs.ba_digraph(40, 2, seed=3)
+        R = O.problem_ref(g.n, g.src, g.dst, hdiag=hdiag)
+        f = lambda r: O.rhs_ref(r, R.H, R.G, R.d, 0.7)
+        a, res, _ = O.steady_null_ref(f, g.n)
+        b, _, _ = O.steady_ref(np.eye(g.n) / g.n, f, 0.01, 1e-13, 400000)
+        assert res < 1e-12 and np.max(np.abs(a - b)) < 1e-11
+        assert abs(np.trace(a) - 1) < 1e-13
