@@ -163,10 +163,10 @@ def tie_aware_rank_check(p_ref, rank, tau, np):
 def accelerated(Q, W, P, params, plain, plain_value, torch, np):
     """RKF45 from the omega-blended learned warm start (inference included)."""
     for w in OMEGAS:  # untimed: first use of the network path (allocations)
-        W.warm_rho0(P, w, params)
+        W.warm_rho0(P, w, params, integrator="rkf45")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = solve_all(Q, P, "fp64", rho0_fn=lambda w: W.warm_rho0(P, w, params),
+    out = solve_all(Q, P, "fp64", rho0_fn=lambda w: W.warm_rho0(P, w, params, integrator="rkf45"),
                     integrator="rkf45")
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / len(OMEGAS)
@@ -178,7 +178,7 @@ def accelerated(Q, W, P, params, plain, plain_value, torch, np):
         viol += tie_aware_rank_check(p_ref, a.rank.cpu().numpy(), 2 * err, np)
     row = {"seconds_per_solve": t, "speedup_vs_plain_fp64": plain_value / t,
            "accepted_steps": [r.stats["steps"] for r in out],
-           "blend_weights": [W.blend_weight(w) for w in OMEGAS],
+           "blend_weights": [W.blend_weight(w, "rkf45") for w in OMEGAS],
            "max_abs_drho_vs_plain": err, "ranking_identical": exact,
            "order_violations_beyond_2maxdrho": viol,
            "residuals": [r.stats["residual"] for r in out]}
@@ -196,10 +196,11 @@ def target_rows(Q, W, P, params, plain, plain_value, torch, np):
     out = {}
     for name, kw in (("batch_mixed_fp32_warm", dict(prec="fp32")),
                      ("batch_rkf45_warm", dict(prec="fp64", integrator="rkf45"))):
-        W.warm_rho0_batch(items, params)          # untimed first use of the network path
+        integ = kw.get("integrator", "rk4")
+        W.warm_rho0_batch(items, params, integrator=integ)  # untimed first use of the network
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rho0s = W.warm_rho0_batch(items, params)
+        rho0s = W.warm_rho0_batch(items, params, integrator=integ)
         rb = Q.batch_solve(items, tol=TOL, want_rank=True, rho0s=rho0s, **kw)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / len(OMEGAS)
@@ -247,8 +248,14 @@ def n4096_rows(Q, inputs, params, torch, np, args):
                                       "rk4_steps": plain.stats["steps"]}}
     log(f"n=4096 plain fp64: {plain.stats['seconds']:.2f} s, {plain.stats['steps']} steps")
     sp_ms, epi_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64", cfg=-2, reps=20)
-    _, fused_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64",
-                                 cfg=-3 - len(Q.SPARSE_VARIANTS), reps=20)
+    nvar = len(Q.SPARSE_VARIANTS)
+    _, fused_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64", cfg=-3 - nvar, reps=20)
+    # the stage of the mixed solve with the defect held in FP32 (the dominant
+    # kernel of the mixed and spec solves at this size): its own
+    # algorithmic bytes are half the FP64 stage's, ~40 B per element (the
+    # gathered stage state 8, y_n 8 and the accumulator 16 over the upper
+    # triangle's two planes, the output 8), and it does the FP64 stage's work
+    _, f32s_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp32", cfg=-3 - (nvar + 2), reps=20)
     # at this size the solves take the fused epilogue (the sparse gathers inside
     # the stage kernel, no X round trip); the two-kernel stage is timed beside it
     row["stage_us"] = {"fused_epilogue": fused_ms * 1e3, "spmm": sp_ms * 1e3,
@@ -258,14 +265,19 @@ def n4096_rows(Q, inputs, params, torch, np, args):
                        "fused_frac_unique_bytes": 50.0 * n * n / (fused_ms * 1e-3) / 1e9 /
                        HBM_PEAK_GBS,
                        "spmm_GBs": 32.0 * n * n / (sp_ms * 1e-3) / 1e9,
-                       "epilogue_GBs": 96.0 * n * n / (epi_ms * 1e-3) / 1e9}
+                       "epilogue_GBs": 96.0 * n * n / (epi_ms * 1e-3) / 1e9,
+                       "fp32_state_stage": f32s_ms * 1e3,
+                       "fp32_state_frac": 40.0 * n * n / (f32s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "fp32_state_frac_fp64_bytes":
+                           80.0 * n * n / (f32s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     runs = {}
     if not args.no_rkf45:
         runs["fp64_rkf45"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, integrator="rkf45")
         if params is not None:
             from paper_2003_04930_amd import warmstart as W
             runs["accelerated"] = lambda: Q.steady_state(
-                Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), integrator="rkf45")
+                Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params, integrator="rkf45"),
+                integrator="rkf45")
     if not args.no_mixed:
         runs["mixed_fp32"] = lambda: Q.steady_state(Pn, w, DT, TOL, 400000, prec="fp32")
         if params is not None:
@@ -344,7 +356,7 @@ def config4_rows(Q, inputs, params, torch, np, mode):
         rho0s = None
         if warm:
             from paper_2003_04930_amd import warmstart as W
-            rho0s = W.warm_rho0_batch(its, params)
+            rho0s = W.warm_rho0_batch(its, params, integrator=kw.get("integrator", "rk4"))
         rb = Q.batch_solve(its, tol=TOL, want_rank=True, rho0s=rho0s, **kw)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
@@ -620,7 +632,7 @@ def main():
             if kw.pop("warm", False):
                 from paper_2003_04930_amd import warmstart as W
                 t0i = time.perf_counter()
-                rho0s = W.warm_rho0_batch(items, params)
+                rho0s = W.warm_rho0_batch(items, params, integrator=kw.get("integrator", "rk4"))
                 torch.cuda.synchronize()
                 t_inf = time.perf_counter() - t0i
             rb = Q.batch_solve(items, tol=TOL, want_rank=True, rho0s=rho0s,

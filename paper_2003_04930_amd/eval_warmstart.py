@@ -87,7 +87,7 @@ def summarise(name, om, cold, pr, warm):
             "ratio_warm_vs_identity": float(np.mean(warm[m] / cold[m])),
             "ratio_pagerank_vs_identity": float(np.mean(pr[m] / cold[m])),
             "ratio_warm_vs_pagerank": float(np.mean(warm[m] / pr[m])),
-            "blend_weight": W.blend_weight(w)}
+            "blend_weight": W.blend_weight(w, name)}
     log(f"{name}: warm/I {out['ratio_warm_vs_identity']:.3f}, PR/I "
         f"{out['ratio_pagerank_vs_identity']:.3f}")
     return out
@@ -118,13 +118,16 @@ def main():
     def pagerank(sl):
         return [W.pagerank_rho0(P) for P, _ in sl]
 
+    integ_now = ["rk4"]
+
     def warm(sl):
-        return W.warm_rho0_batch(sl, params)
+        return W.warm_rho0_batch(sl, params, integrator=integ_now[0])
 
     summary = {"graphs": len(items), "n_max": args.n_max, "tol": TOL,
                "n_quartiles": [int(x) for x in np.percentile([g.n for g in graphs],
                                                             [0, 25, 50, 75, 100])]}
     for integ, count in (("rkf45", len(items)), ("rk4", min(args.rk4_graphs, len(items)))):
+        integ_now[0] = integ
         sub = items[:count]
         res = {}
         for name, fn in (("identity", identity), ("pagerank", pagerank), ("warm", warm)):
