@@ -252,9 +252,10 @@ def n4096_rows(Q, inputs, params, torch, np, args):
     _, fused_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64", cfg=-3 - nvar, reps=20)
     # the stage of the mixed solve with the defect held in FP32 (the dominant
     # kernel of the mixed and spec solves at this size): its own
-    # algorithmic bytes are half the FP64 stage's, ~40 B per element (the
-    # gathered stage state 8, y_n 8 and the accumulator 16 over the upper
-    # triangle's two planes, the output 8), and it does the FP64 stage's work
+    # algorithmic bytes are half the FP64 stage's 80 B per element, 40 B (the
+    # stage state read 8, y_n 8, the accumulator read and written 8 + 8, the
+    # output 8: two FP32 planes each, counted as the FP64 figure counts them),
+    # and it does the FP64 stage's work
     _, f32s_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp32", cfg=-3 - (nvar + 2), reps=20)
     # at this size the solves take the fused epilogue (the sparse gathers inside
     # the stage kernel, no X round trip); the two-kernel stage is timed beside it
