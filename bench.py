@@ -13,15 +13,21 @@ per solve is `extra.seconds_per_solve_fp64`.
 
 Also reported (same graph, same omegas): the paper's adaptive RKF45
 integrator, the accelerated solver (RKF45 from the learned, omega-blended
-warm start) with its ranking checked against the plain solve, the dense FP64
-MFMA solve, the mixed-precision solves (BF16x3 and FP32 MFMA products with
-FP64 judge), the same comparison at N = 4096 (BA m=4, omega = 0.8), the
-roofline of the dominant kernel of the timed path (timed with HIP events on
-the stream the kernels run on), and the CPU oracle on a bounded sample of the
-workload.
+warm start) with its ranking checked against the plain solve, the
+spec form (qpr_batch_solve, FP32 steps with the defect held in FP32 and
+the FP64 fold and judge, from the warm start), the dense FP64 MFMA solve, the
+mixed-precision solves (BF16x3 and FP32 products with FP64 judge); the same
+comparison at N = 4096 (BA m=4, omega = 0.8) and the plain solve at N = 2048;
+hub classes and degeneracy of PageRank against the quantum steady state at
+each size; the 1,280-system batching workload (--config4); the roofline of the
+dominant kernel of the timed path (timed alone with HIP events on the stream
+the kernel runs on, on the hot-path scope's bytes per element, with the
+aggregate rate of the whole timed region beside it); and the CPU oracle on a
+bounded sample of the workload (host CPU model, core count and BLAS stated).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mixed]
                     [--no-dense] [--no-rkf45] [--no-4096] [--warm PATH|none]
+                    [--config4 off|subset|full]
 """
 from __future__ import annotations
 
@@ -45,11 +51,11 @@ BF16_PEAK_TFLOPS = 2500.0
 # HBM bytes per launch at this workload from rocprofv3 FETCH_SIZE (x2.00) and
 # WRITE_SIZE (x1.00) passes, the factors calibrated on a 256 MiB copy; valid
 # for the stage kernels in the source with this sha256 prefix only (the
-# summary with the commands: profiles/sparse_stage_hbm_counters_n922_n4096.md)
-COUNTERS_SRC = ("paper_2003_04930_amd/csrc/qpr_step.hip", "85f8d498b85043bd")
-TRAFFIC_N922 = {"epilogue": (16480.4 * 2.0 + 19992.7) * 1024.0,
-                "spmm": (7369.9 * 2.0 + 13830.0) * 1024.0,
-                "fused": (22033.7 * 2.0 + 19990.2) * 1024.0}
+# summary with the commands: profiles/rk4_stage_kernels_n922_n4096.md)
+COUNTERS_SRC = ("paper_2003_04930_amd/csrc/qpr_step.hip", "757e593ec9a862fd")
+TRAFFIC_N922 = {"epilogue": (16497.6 * 2.0 + 19992.7) * 1024.0,
+                "spmm": (7355.1 * 2.0 + 13830.0) * 1024.0,
+                "fused": (22033.0 * 2.0 + 19990.2) * 1024.0}
 
 
 def measured_traffic(kernel):
