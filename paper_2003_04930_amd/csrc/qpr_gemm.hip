@@ -26,6 +26,12 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+// Staging registers of the k-slab prefetch are native vectors: arrays of
+// HIP's struct vector types (uint4, double2, float4) are not split into
+// registers by the compiler and go through scratch memory, which makes every
+// prefetch wait for its loads at once.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 // Bijective map from the hardware workgroup id (dispatched round-robin over
 // the 8 XCDs) to a logical tile id such that each XCD receives a contiguous
@@ -45,7 +51,7 @@ struct MfmaK4;
 template <>
 struct MfmaK4<double> {
   typedef d4 acc_t;
-  typedef double2 vec_t;
+  typedef d2v vec_t;
   static constexpr int EV = 2;
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -55,7 +61,7 @@ struct MfmaK4<double> {
 template <>
 struct MfmaK4<float> {
   typedef f4 acc_t;
-  typedef float4 vec_t;
+  typedef f4 vec_t;
   static constexpr int EV = 4;
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -273,7 +279,7 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
   constexpr int BK = 32;          // one MFMA depth
   constexpr int RS = BK + 8;      // padded LDS row (bf16 elements): 80 bytes
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int NA = BM * (BK / 8) / NT;      // uint4 loads per thread, A
+  constexpr int NA = BM * (BK / 8) / NT;      // 16-byte loads per thread, A
   constexpr int NB = BN * (BK / 8) / NT;      // per plane-slice, B
   static_assert(NA * NT == BM * BK / 8 && NB * NT == BN * BK / 8, "tile/thread mismatch");
   __shared__ uint16_t As[2][BM * RS];
@@ -295,33 +301,33 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[p][i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ra[NA], rb[6][NB];
+  u4v ra[NA], rb[6][NB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
-      ra[u] = *reinterpret_cast<const uint4*>(H + (size_t)(m0 + row) * ld + k0 + 8 * c);
+      ra[u] = *reinterpret_cast<const u4v*>(H + (size_t)(m0 + row) * ld + k0 + 8 * c);
     }
 #pragma unroll
     for (int ps = 0; ps < 6; ++ps)
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
-        rb[ps][u] = *reinterpret_cast<const uint4*>(sl + ps * plane + (size_t)(n0 + row) * ld + k0 + 8 * c);
+        rb[ps][u] = *reinterpret_cast<const u4v*>(sl + ps * plane + (size_t)(n0 + row) * ld + k0 + 8 * c);
       }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
-      *reinterpret_cast<uint4*>(&As[buf][row * RS + 8 * c]) = ra[u];
+      *reinterpret_cast<u4v*>(&As[buf][row * RS + 8 * c]) = ra[u];
     }
 #pragma unroll
     for (int ps = 0; ps < 6; ++ps)
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int v = tid + u * NT, row = v / (BK / 8), c = v % (BK / 8);
-        *reinterpret_cast<uint4*>(&Bs[buf][ps][row * RS + 8 * c]) = rb[ps][u];
+        *reinterpret_cast<u4v*>(&Bs[buf][ps][row * RS + 8 * c]) = rb[ps][u];
       }
   };
 
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
   constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
   constexpr int BK = 32, RS = BK + 8;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int UA = BM * (BK / 8), UB = 6 * BN * (BK / 8);  // uint4 units per slab
+  constexpr int UA = BM * (BK / 8), UB = 6 * BN * (BK / 8);  // u4v units per slab
   constexpr int NA = (UA + NT - 1) / NT, NB = (UB + NT - 1) / NT;
   __shared__ uint16_t As[BM * RS];
   __shared__ uint16_t Bs[6 * BN * RS];
@@ -404,20 +410,20 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[p][i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ra[NA], rb[NB];
+  u4v ra[NA], rb[NB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int v = tid + u * NT;
       if (UA % NT == 0 || v < UA)
-        ra[u] = *reinterpret_cast<const uint4*>(H + (size_t)(m0 + v / 4) * ld + k0 + 8 * (v % 4));
+        ra[u] = *reinterpret_cast<const u4v*>(H + (size_t)(m0 + v / 4) * ld + k0 + 8 * (v % 4));
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int v = tid + u * NT;
       if (UB % NT == 0 || v < UB) {
         const int ps = v / (BN * 4), rem = v % (BN * 4);
-        rb[u] = *reinterpret_cast<const uint4*>(sl + ps * plane + (size_t)(n0 + rem / 4) * ld +
+        rb[u] = *reinterpret_cast<const u4v*>(sl + ps * plane + (size_t)(n0 + rem / 4) * ld +
                                                 k0 + 8 * (rem % 4));
       }
     }
@@ -427,14 +433,14 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
     for (int u = 0; u < NA; ++u) {
       const int v = tid + u * NT;
       if (UA % NT == 0 || v < UA)
-        *reinterpret_cast<uint4*>(&As[(v / 4) * RS + 8 * (v % 4)]) = ra[u];
+        *reinterpret_cast<u4v*>(&As[(v / 4) * RS + 8 * (v % 4)]) = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int v = tid + u * NT;
       if (UB % NT == 0 || v < UB) {
         const int ps = v / (BN * 4), rem = v % (BN * 4);
-        *reinterpret_cast<uint4*>(&Bs[(ps * BN + rem / 4) * RS + 8 * (rem % 4)]) = rb[u];
+        *reinterpret_cast<u4v*>(&Bs[(ps * BN + rem / 4) * RS + 8 * (rem % 4)]) = rb[u];
       }
     }
   };
@@ -485,6 +491,132 @@ __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
   }
 }
 
+// 32 x 32 x 16 form of the BF16x3 product (v_mfma_f32_32x32x16_bf16).  One
+// instruction makes a 32 x 32 block from a 32 x 16 fragment of each operand:
+// half the operand bytes per flop of the 16 x 16 x 32 form above, whose LDS
+// reads (one A and one B fragment per 16 x 16 block) kept the matrix cores
+// about a fifth busy.  Lane l supplies A[l%32][8(l/32) .. +7] and
+// B[8(l/32) .. +7][l%32]; accumulator register r of lane l holds
+// D[8(r/4) + 4(l/32) + r%4][l%32].  Each 32-deep k-slab is two instructions
+// deep; slabs are double buffered in LDS (the next slab's global loads are in
+// flight, in registers, while the current one is multiplied; then they go to
+// the other buffer and one barrier ends the slab).  Within an instruction the
+// products are summed sixteen at a time instead of thirty-two, so this family
+// agrees with the 16 x 16 x 32 one within FP32 rounding, not bitwise; its own
+// tile shapes agree bitwise with each other (same slice order, same k order).
+typedef float f16v __attribute__((ext_vector_type(16)));
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+    k_gemm_bf16x3_m32(const uint16_t* __restrict__ H, const uint16_t* __restrict__ sl,
+                      float* __restrict__ Xr, float* __restrict__ Xi, int ld,
+                      const DevState* __restrict__ st, int gate) {
+  constexpr int NWM = BM / WM, NWN = BN / WN, NT = NWM * NWN * 64;
+  constexpr int BK = 32, RS = BK + 8;  // padded LDS row: 80 bytes
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int UA = BM * (BK / 8), UB = 6 * BN * (BK / 8);  // 16-byte units per slab
+  constexpr int NA = UA / NT, NB = UB / NT;
+  static_assert(NA * NT == UA && NB * NT == UB, "slab units must divide over the threads");
+  static_assert(FM * 32 == WM && FN * 32 == WN, "wave tiles are multiples of 32");
+  __shared__ uint16_t As[2][BM * RS];
+  __shared__ uint16_t Bs[2][6 * BN * RS];
+  if (st->stop || (gate && st->hold)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = ld / BM;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (logical % tiles_m) * BM, n0 = (logical / tiles_m) * BN;
+  const int wm0 = (wave % NWM) * WM, wn0 = (wave / NWM) * WN;
+  const size_t plane = (size_t)ld * ld;
+
+  f16v acc[2][FM][FN];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
+
+  // unit v of a slab: A row v / 4 (rows of H), else B slice ps = v' / (4 BN),
+  // row v' % (4 BN) / 4; 16-byte chunk v % 4 of the row's 32 k values
+  u4v ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT;
+      ra[u] = *reinterpret_cast<const u4v*>(H + (size_t)(m0 + v / 4) * ld + k0 + 8 * (v % 4));
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT;
+      const int ps = v / (BN * 4), rem = v % (BN * 4);
+      rb[u] = *reinterpret_cast<const u4v*>(sl + ps * plane + (size_t)(n0 + rem / 4) * ld + k0 +
+                                              8 * (rem % 4));
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int v = tid + u * NT;
+      *reinterpret_cast<u4v*>(&As[buf][(v / 4) * RS + 8 * (v % 4)]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + u * NT;
+      const int ps = v / (BN * 4), rem = v % (BN * 4);
+      *reinterpret_cast<u4v*>(&Bs[buf][(ps * BN + rem / 4) * RS + 8 * (rem % 4)]) = rb[u];
+    }
+  };
+
+  const int KT = ld / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int lr = lane >> 5, lc = lane & 31;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf8 a[FM];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const bf8*>(&As[buf][(wm0 + i * 32 + lc) * RS + kk + 8 * lr]);
+#pragma unroll
+      for (int ps = 0; ps < 6; ++ps) {
+        const int p = ps / 3;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const bf8 b = *reinterpret_cast<const bf8*>(
+              &Bs[buf][(ps * BN + wn0 + j * 32 + lc) * RS + kk + 8 * lr]);
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+            acc[p][i][j] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[p][i][j], 0, 0, 0);
+        }
+      }
+    }
+    if (kt + 1 < KT) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    float* X = p ? Xi : Xr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm0 + i * 32 + 8 * (r / 4) + 4 * lr + (r % 4);
+          const int col = n0 + wn0 + j * 32 + lc;
+          X[(size_t)row * ld + col] = acc[p][i][j][r];
+        }
+  }
+}
+
 template <typename Fn>
 struct GemmCfg {
   int bm, bn;
@@ -529,6 +661,14 @@ const GemmCfg<BFFn> kBF[] = {
     {256, 64, "bf16x3_256x64_w64x32_sb", k_gemm_bf16x3_sb<256, 64, 64, 32>, 512},
     {128, 128, "bf16x3_128x128_w64x64_sb", k_gemm_bf16x3_sb<128, 128, 64, 64>, 256},
     {256, 128, "bf16x3_256x128_w64x64_sb", k_gemm_bf16x3_sb<256, 128, 64, 64>, 512},
+    // 32 x 32 x 16 family (configurations 8..)
+    {64, 64, "bf16x3_m32_64x64_w32x32", k_gemm_bf16x3_m32<64, 64, 32, 32>, 256},
+    {128, 64, "bf16x3_m32_128x64_w64x32", k_gemm_bf16x3_m32<128, 64, 64, 32>, 256},
+    {128, 64, "bf16x3_m32_128x64_w32x32", k_gemm_bf16x3_m32<128, 64, 32, 32>, 512},
+    {256, 64, "bf16x3_m32_256x64_w64x32", k_gemm_bf16x3_m32<256, 64, 64, 32>, 512},
+    {256, 64, "bf16x3_m32_256x64_w128x32", k_gemm_bf16x3_m32<256, 64, 128, 32>, 256},
+    {128, 128, "bf16x3_m32_128x128_w64x32", k_gemm_bf16x3_m32<128, 128, 64, 32>, 512},
+    {128, 128, "bf16x3_m32_128x128_w64x64", k_gemm_bf16x3_m32<128, 128, 64, 64>, 256},
 };
 // block-sparse tiles: 32 rows (the slab-list granularity) x BN columns
 typedef void (*F64BsFn)(const double*, const double*, const double*, double*, double*, int,
@@ -612,16 +752,20 @@ int gemm_default_cfg(int kind, int n) {
       best_ld = e.ld;
     }
   if (best >= 0) return best;
-  // untuned defaults, from HIP-event sweeps on MI355X at N = 922, 2048, 4096:
-  // small problems want more, smaller tiles; large ones 128-row tiles
+  // untuned defaults, from HIP-event sweeps on MI355X at N = 922, 1024, 1536,
+  // 2048, 4096: small problems want more, smaller tiles; large ones 128-row
+  // tiles (FP64 128x64: 4.03 ms at 4096, 0.87 of the FP64 peak; FP32 128x64:
+  // 2.03 ms, 0.86)
   const bool big = ld >= 2048 && ld % 128 == 0;
   if (kind == OP_F64) return big ? 10 : 1;
-  if (kind == OP_F32) return big ? 0 : 5;
-  // BF16x3: single-LDS-buffer tiles with 256 rows of H where ld allows
-  // (4096: 256x128, 1.88 ms; 2048: 256x64, 0.23 ms)
+  if (kind == OP_F32) return big ? 2 : 5;
+  // BF16x3: 256 rows of H where ld allows -- the single-LDS-buffer 256x128
+  // tile at 4096 (0.68 ms, 0.48 of the bf16 peak), the 32x32x16 256x64 tile
+  // from 1536 (65 us; 92 us at 2048) -- else the 32x32x16 64x64 tile, which
+  // divides every ld (25 us at 922 and 1024)
   if (ld % 256 == 0 && ld >= 4096) return 7;
-  if (ld % 256 == 0 && ld >= 2048) return 5;
-  return big ? 3 : 0;
+  if (ld % 256 == 0 && ld >= 1536) return 11;
+  return 8;
 }
 
 template <typename C>

@@ -110,7 +110,9 @@ def test_lowp_rk4_trajectory_close_to_fp64(Q):
 def test_every_dense_tile_configuration(Q, prec):
     """Every tile configuration of the dense product runs the MFMA
     accumulation along k in the same order (and, for BF16x3, the slices in the
-    same order), so all give bitwise the same right-hand side; it matches the
+    same order), so all configurations of one instruction shape give bitwise
+    the same right-hand side (BF16x3 has two: 16 x 16 x 32 and, named _m32_,
+    32 x 32 x 16, which sums the products in sixteens); every one matches the
     oracle within the precision's bound.  N = 250 pads to ld = 256, which every
     tile shape divides."""
     g = inputs.ba_digraph(250, 3, seed=21)
@@ -127,8 +129,13 @@ def test_every_dense_tile_configuration(Q, prec):
         got = Q.to_complex(Q.rhs(P, 0.4, Q.planar(rho), prec=prec, product="dense", gemm_cfg=cfg))
         assert np.max(np.abs(got - want)) <= bound, name
         outs.append(got)
-    for name, got in zip(names[1:], outs[1:]):
-        assert np.array_equal(got, outs[0]), name
+    first = {}
+    for name, got in zip(names, outs):
+        family = "_m32_" in name
+        if family in first:
+            assert np.array_equal(got, first[family]), name
+        else:
+            first[family] = got
 
 
 @pytest.mark.parametrize("name,n,m", [("ba130", 130, 3), ("ba922", 922, 3)])
