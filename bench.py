@@ -410,6 +410,8 @@ def main():
     import numpy as np
     import torch
     from paper_2003_04930_amd import inputs, qpr as Q
+    # the batch solves report how many systems have finished every 30 s
+    os.environ.setdefault("QPR_PROGRESS", "30")
 
     torch.cuda.set_device(0)
     g = inputs.ba_digraph(N, M_BA, seed=0)

@@ -327,6 +327,9 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
  * Errors: those of qpr_steady_state, QPR_E_ARG (count < 1, nworkers out of
  * range, NULL arrays, a repeated stream), QPR_E_WORKSPACE (a workspace too
  * small for the largest system).  Returns when every system has finished.
+ * With the environment variable QPR_PROGRESS set to a number of seconds, the
+ * count of finished systems is printed to stderr at most that often (and
+ * when the last one finishes); unset, nothing is printed.
  */
 qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
                                  const double* omegas, double dt, double tol,
@@ -365,7 +368,9 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *    decided on the largest system's density for the whole batch (with AUTO the sparse
  *    stages, FP64 and FP32, run as fused epilogues); the dense-product tile
  *    configuration is tuned on this batch's own work list unless
- *    opts->gemm_cfg >= 0.  Also bitwise the lone solves.
+ *    opts->gemm_cfg >= 0.  FP64: bitwise the lone solves; FP32: the defect
+ *    is held in FP64 whatever opts->delta_state says (the lone FP32 solve's
+ *    default holds it in FP32, so step counts can differ slightly).
  *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are
  *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
  *           may be NULL or hold device int32[n_k] / NULL entries
@@ -378,7 +383,9 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *           the process's current tuning
  * Errors: QPR_E_ARG, QPR_E_UNSTABLE, QPR_E_WORKSPACE, QPR_E_HIP, and after a
  * full run QPR_E_NONFINITE / QPR_E_NOT_CONVERGED if any system failed.
- * Synchronises once per chunk.
+ * Synchronises once per chunk.  QPR_PROGRESS=<seconds> in the environment
+ * prints the count of finished (concurrent) or stopped (persistent) systems
+ * to stderr at most that often, as qpr_steady_state_many does.
  */
 qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* probs,
                            const double* omegas, double dt, double tol,

@@ -606,6 +606,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   hipGraphExec_t exec = exec_h.h;
   std::vector<DevState> hs(nsys);
   qpr_status rc = QPR_OK;
+  Progress progress("persistent batch");
   for (;;) {
     hipError_t e = o.use_graph ? hipGraphLaunch(exec, s) : enqueue_chunk(s);
     if (e == hipSuccess)
@@ -625,6 +626,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       }
       running += a;
     }
+    progress.report(nsys - running, nsys, "stopped");
     if (!running) break;
     if (changed) {
       build_lists();

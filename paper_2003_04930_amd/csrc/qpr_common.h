@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "../../include/qpr.h"
@@ -326,5 +330,34 @@ const char* gemm_cfg_name(int kind, int cfg);
 int gemm_default_cfg(int kind, int n);
 void gemm_set_tuned(int kind, int ld, int cfg);
 bool gemm_cfg_fits(int kind, int cfg, int ld);
+
+// Progress of a long batch on stderr, for callers that watch a run's output:
+// with QPR_PROGRESS=<seconds> set, report() prints "done of total" at most
+// once per that interval (and always for the last one); unset, it prints
+// nothing.  Safe to call from several worker threads.
+class Progress {
+ public:
+  explicit Progress(const char* what) : what_(what), t0_(std::chrono::steady_clock::now()) {
+    const char* e = std::getenv("QPR_PROGRESS");
+    every_ = e ? std::atof(e) : 0.0;
+  }
+  void report(int done, int total, const char* unit) {
+    if (every_ <= 0.0) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    const double t =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+    if (done < total && t - last_ < every_) return;
+    last_ = t;
+    std::fprintf(stderr, "[qpr] %s: %d of %d systems %s after %.0f s\n", what_, done, total, unit,
+                 t);
+    std::fflush(stderr);
+  }
+
+ private:
+  const char* what_;
+  std::chrono::steady_clock::time_point t0_;
+  double every_ = 0.0, last_ = 0.0;
+  std::mutex mu_;
+};
 
 }  // namespace qpr

@@ -1013,6 +1013,7 @@ qpr_status qpr::run_many(int count, const qpr_problem* const* probs, const doubl
   conc.remaining.store(count);
   conc.workers = nworkers;
   std::atomic<int> next(0);
+  Progress progress("concurrent batch");
   auto work = [&](int w) {
     bool dev_ok = hipSetDevice(dev) == hipSuccess;
     // this worker's pinned control-block copies, for all of its systems
@@ -1032,8 +1033,9 @@ qpr_status qpr::run_many(int count, const qpr_problem* const* probs, const doubl
                                       streams[w], &conc, (DevState*)pin.h);
         if (status[k] != QPR_OK) msg[k] = qpr_last_error();
       }
-      conc.remaining.fetch_sub(1, std::memory_order_relaxed);
+      const int left = conc.remaining.fetch_sub(1, std::memory_order_relaxed) - 1;
       local[k].status = status[k];
+      progress.report(count - left, count, "solved");
     }
   };
   // a worker that cannot be started runs on the calling thread
