@@ -4,13 +4,17 @@ each re-measured by the CPU FP64 oracle.
 
 For each solver the oracle's right-hand side gives the residual of the
 returned state (it must be below the tolerance), and the state must be trace
-one, bitwise Hermitian and positive semidefinite.  The oracle integrating to
-1e-8 here would take hours on the host, so the low-precision solves are
-compared with the plain FP64 GPU solve, whose residual the oracle has just
-confirmed: max |d rho| below the 1e-6 bound of the mixed solves, and the
+one, bitwise Hermitian and positive semidefinite.  The low-precision solves
+are compared with the plain FP64 GPU solve, whose residual the oracle has
+just confirmed: max |d rho| below the 1e-6 bound of the mixed solves, and the
 ranking equal on every pair whose gap exceeds 2 max |d rho| (closer pairs
-are tie classes, compared only as a count).  The smallest eigenvalue of the
-plain state is computed (eigvalsh); for the others Weyl's inequality
+are tie classes, compared only as a count).  At N = 4096 every solve is also
+compared with the oracle's own steady state (tests/golden/
+ss_ba4096_w08_diag.txt, the GMRES null vector of L written by
+make_ss_ba4096.py from oracle/ only): populations within 1e-6 and the
+oracle's ranking on every pair whose oracle gap exceeds twice the measured
+population error.  The smallest eigenvalue of the plain state is computed
+(eigvalsh); for the others Weyl's inequality
 lambda_min(rho) >= lambda_min(rho_plain) - ||rho - rho_plain||_F bounds it.
 """
 import os
@@ -25,8 +29,25 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 OMEGA, DT, TOL = 0.8, 0.01, 1e-8
-WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2003_04930_amd", "weights", "mpnn_warmstart.npy")
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2003_04930_amd", "weights",
+                       "mpnn_warmstart.npy")
+GOLDEN_4096 = os.path.join(HERE, "golden", "ss_ba4096_w08_diag.txt")
+
+
+def oracle_populations(n):
+    """The oracle's steady-state populations where they are stored (N = 4096)."""
+    if n != 4096:
+        return None
+    p = []
+    with open(GOLDEN_4096) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                p.append(float(line.split()[1]))
+    p = np.array(p)
+    assert p.shape == (n,)
+    return p
 
 
 @pytest.fixture(scope="module")
@@ -62,6 +83,18 @@ def oracle_checks(R, rho):
     assert np.array_equal(rho, rho.conj().T)
 
 
+def against_oracle_steady_state(n, rho, rank):
+    """Max population error against the oracle's steady state and its ranking
+    on every pair the error resolves; None where none is stored."""
+    p_or = oracle_populations(n)
+    if p_or is None:
+        return None
+    err = float(np.max(np.abs(np.diag(rho).real - p_or)))
+    assert err < 1e-6, err
+    assert tie_aware_same_order(p_or, rank, 2 * err + 1e-15) == 0
+    return err
+
+
 def tie_aware_same_order(p_ref, rank, tau):
     """Number of pairs with p_ref gap > tau whose order `rank` reverses."""
     n = p_ref.size
@@ -88,6 +121,8 @@ def test_config3_plain_fp64(Q, n):
     assert plain.stats["herm_err"] == 0.0
     # the GPU's ranking of its own state is the oracle's rank rule (exact)
     assert np.array_equal(plain.rank.cpu().numpy(), O.rank_ref(np.diag(rho).real))
+    err = against_oracle_steady_state(n, rho, plain.rank.cpu().numpy())
+    assert err is None or err < 1e-7, err
 
 
 def _compare_with_plain(Q, n, got_rho, got_rank):
@@ -99,6 +134,7 @@ def _compare_with_plain(Q, n, got_rho, got_rank):
     assert lmin - np.linalg.norm(a - rho) >= -1e-12
     p_ref = np.diag(rho).real
     assert tie_aware_same_order(p_ref, got_rank.cpu().numpy(), 2 * d + 1e-15) == 0
+    against_oracle_steady_state(n, a, got_rank.cpu().numpy())
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
