@@ -504,7 +504,8 @@ qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t reps,
 /* Load a cache written by qpr_autotune (later lines win). */
 qpr_status qpr_load_tuning(const char* cache_path);
 
-/* Number of product tile configurations at precision prec, and their names. */
+/* Number of product tile configurations at precision prec (0 for an unknown
+ * precision), and their names ("?" for an unknown precision or index). */
 int32_t qpr_product_configs(int32_t prec);
 const char* qpr_product_config_name(int32_t prec, int32_t cfg);
 

@@ -1169,14 +1169,20 @@ extern "C" qpr_status qpr_time_kernels(const qpr_problem* P, double omega, int32
   return QPR_OK;
 }
 
-extern "C" int32_t qpr_product_configs(int32_t prec) { return gemm_num_cfgs(op_kind(prec)); }
+static bool known_prec(int32_t prec) {
+  return prec == QPR_FP64 || prec == QPR_FP32 || prec == QPR_BF16X3;
+}
+
+extern "C" int32_t qpr_product_configs(int32_t prec) {
+  return known_prec(prec) ? gemm_num_cfgs(op_kind(prec)) : 0;
+}
 
 extern "C" int32_t qpr_sparse_variants(void) { return spmm_num_variants(); }
 
 extern "C" const char* qpr_sparse_variant_name(int32_t v) { return spmm_variant_name(v); }
 
 extern "C" const char* qpr_product_config_name(int32_t prec, int32_t cfg) {
-  return gemm_cfg_name(op_kind(prec), cfg);
+  return known_prec(prec) ? gemm_cfg_name(op_kind(prec), cfg) : "?";
 }
 
 extern "C" qpr_status qpr_autotune(const qpr_problem* P, int32_t prec, int32_t reps,

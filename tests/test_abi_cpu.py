@@ -197,3 +197,22 @@ def test_load_tuning_parses_every_entry_kind(tmp_path):
     bad.write_text("10 960 99 1.0 none\n11 960 7 1.0 none\n3 960 0 1.0 none\n0 100 0 1.0 odd\n")
     assert L.qpr_load_tuning(str(bad).encode()) == qpr.QPR_E_ARG
     assert L.qpr_load_tuning(str(tmp_path / "absent.txt").encode()) == qpr.QPR_E_ARG
+
+
+def test_product_configuration_tables():
+    """Host-side tables of the dense-product tile configurations: names are
+    unique per precision, and the BF16x3 table holds both MFMA families (the
+    32 x 32 x 16 ones named _m32_), whose results agree only within the
+    family (the GPU test checks the values)."""
+    _lib()
+    counts = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        names = qpr.product_configs(prec)
+        assert len(names) == len(set(names)) and len(names) >= 6, prec
+        assert all(n.startswith(prec.replace("fp", "f")) or n.startswith(prec) for n in names)
+        counts[prec] = names
+    bf = counts["bf16x3"]
+    assert any("_m32_" in n for n in bf) and any("_m32_" not in n for n in bf)
+    assert qpr.lib().qpr_product_configs(99) == 0
+    assert qpr.lib().qpr_product_config_name(99, 0) == b"?"
+    assert qpr.lib().qpr_product_config_name(0, 10 ** 6) == b"?"
