@@ -14,12 +14,12 @@ per solve is `extra.seconds_per_solve_fp64`.
 Also reported (same graph, same omegas): the paper's adaptive RKF45
 integrator, the accelerated solver (RKF45 from the learned, omega-blended
 warm start) with its ranking checked against the plain solve, the
-spec form (qpr_batch_solve, FP32 steps with the defect held in FP32 and
+batched mixed warm-start form (qpr_batch_solve, FP32 steps with the defect held in FP32 and
 the FP64 fold and judge, from the warm start), the dense FP64 MFMA solve, the
 mixed-precision solves (BF16x3 and FP32 products with FP64 judge); the same
 comparison at N = 4096 (BA m=4, omega = 0.8) and the plain solve at N = 2048;
 hub classes and degeneracy of PageRank against the quantum steady state at
-each size; the 1,280-system batching workload (--config4); the roofline of the
+each size; the 1,280-system batching workload (--batch-family); the roofline of the
 dominant kernel of the timed path (timed alone with HIP events on the stream
 the kernel runs on, on the hot-path scope's bytes per element, with the
 aggregate rate of the whole timed region beside it); and the CPU oracle on a
@@ -27,7 +27,7 @@ bounded sample of the workload (host CPU model, core count and BLAS stated).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mixed]
                     [--no-dense] [--no-rkf45] [--no-4096] [--warm PATH|none]
-                    [--config4 off|subset|full]
+                    [--batch-family off|subset|full]
 """
 from __future__ import annotations
 
@@ -257,7 +257,7 @@ def n4096_rows(Q, inputs, params, torch, np, args):
     nvar = len(Q.SPARSE_VARIANTS)
     _, fused_ms = Q.time_kernels(Pn, w, plain.rho, prec="fp64", cfg=-3 - nvar, reps=20)
     # the stage of the mixed solve with the defect held in FP32 (the dominant
-    # kernel of the mixed and spec solves at this size): its own
+    # kernel of the mixed and batched warm-start solves at this size): its own
     # algorithmic bytes are half the FP64 stage's 80 B per element, 40 B (the
     # stage state read 8, y_n 8, the accumulator read and written 8 + 8, the
     # output 8: two FP32 planes each, counted as the FP64 figure counts them),
@@ -293,7 +293,7 @@ def n4096_rows(Q, inputs, params, torch, np, args):
             runs["mixed_fp32_warm"] = lambda: Q.steady_state(
                 Pn, w, DT, TOL, 400000, rho0=W.warm_rho0(Pn, w, params), prec="fp32")
 
-            # the spec form: qpr_batch_solve, FP32 steps with the FP64
+            # the batched mixed warm-start form: qpr_batch_solve, FP32 steps with the FP64
             # fold and judge, from the learned warm start (inference included)
             def batch_warm():
                 rb = Q.batch_solve([(Pn, w)], tol=TOL, prec="fp32",
@@ -339,7 +339,7 @@ def n2048_rows(Q, inputs, torch, np):
             "study": study.hub_study(Q, Pn, plain.rho, 2 * err)}
 
 
-def config4_rows(Q, inputs, params, torch, np, mode):
+def batch_family_rows(Q, inputs, params, torch, np, mode):
     """The batching workload: 256 family graphs (N uniform in [50, 922], half
     ER with mean out-degree 4, half BA with m in 2..5) x 5 omegas = 1,280
     systems to ||L|| < 1e-8.  "subset": FP64 RKF45 from the warm start over
@@ -373,7 +373,7 @@ def config4_rows(Q, inputs, params, torch, np, mode):
                      "steps_min_mean_max": [min(st), float(np.mean(st)), max(st)],
                      "max_residual": res,
                      "all_converged": all(x["converged"] == 1 for x in rb.stats)}
-        log(f"config4 {name}: {len(its)} systems in {secs:.1f} s ({len(its) / secs:.1f} solves/s)")
+        log(f"batch family {name}: {len(its)} systems in {secs:.1f} s ({len(its) / secs:.1f} solves/s)")
         del rb
     return out
 
@@ -395,8 +395,8 @@ def main():
                     help="comma list of batched rows to time")
     ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "concurrent"],
                     help="how qpr_batch_solve runs the --batch-graphs systems")
-    ap.add_argument("--config4", default="subset", choices=["off", "subset", "full"],
-                    help="the 1,280-system batching workload (see config4_rows)")
+    ap.add_argument("--batch-family", default="subset", choices=["off", "subset", "full"],
+                    help="the 1,280-system batching workload (see batch_family_rows)")
     ap.add_argument("--precision-n", type=int, default=0,
                     help="also compare FP64 with FP32/BF16x3 products at this N (BA m=4)")
     ap.add_argument("--warm", default=WEIGHTS,
@@ -619,8 +619,8 @@ def main():
                 "speedup_vs_fp64": value / tm}
             log(f"{prec}: {tm:.3f} s/solve, max|drho| {err:.2e}, product {pm * 1e3:.1f} us")
 
-    if args.config4 != "off":
-        extra["config4"] = config4_rows(Q, inputs, params, torch, np, args.config4)
+    if args.batch_family != "off":
+        extra["batch_family"] = batch_family_rows(Q, inputs, params, torch, np, args.batch_family)
 
     if args.batch_graphs:
         items = []

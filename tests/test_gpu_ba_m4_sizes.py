@@ -8,12 +8,11 @@ one, bitwise Hermitian and positive semidefinite.  The low-precision solves
 are compared with the plain FP64 GPU solve, whose residual the oracle has
 just confirmed: max |d rho| below the 1e-6 bound of the mixed solves, and the
 ranking equal on every pair whose gap exceeds 2 max |d rho| (closer pairs
-are tie classes, compared only as a count).  At N = 4096 every solve is also
-compared with the oracle's own steady state (tests/golden/
-ss_ba4096_w08_diag.txt, the GMRES null vector of L written by
-make_ss_ba4096.py from oracle/ only): populations within 1e-6 and the
-oracle's ranking on every pair whose oracle gap exceeds twice the measured
-population error.  The smallest eigenvalue of the plain state is computed
+are tie classes, compared only as a count).  Every solve is also compared
+with the oracle's own steady state (tests/golden/ss_ba<N>_w08_diag.txt, the
+GMRES null vector of L written by make_ss_ba_w08.py from oracle/ only):
+populations within 1e-6 and the oracle's ranking on every pair whose oracle
+gap exceeds twice the measured population error.  The smallest eigenvalue of the plain state is computed
 (eigvalsh); for the others Weyl's inequality
 lambda_min(rho) >= lambda_min(rho_plain) - ||rho - rho_plain||_F bounds it.
 """
@@ -32,15 +31,12 @@ OMEGA, DT, TOL = 0.8, 0.01, 1e-8
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2003_04930_amd", "weights",
                        "mpnn_warmstart.npy")
-GOLDEN_4096 = os.path.join(HERE, "golden", "ss_ba4096_w08_diag.txt")
 
 
 def oracle_populations(n):
-    """The oracle's steady-state populations where they are stored (N = 4096)."""
-    if n != 4096:
-        return None
+    """The oracle's steady-state populations of the size-n workload graph."""
     p = []
-    with open(GOLDEN_4096) as fh:
+    with open(os.path.join(HERE, "golden", f"ss_ba{n}_w08_diag.txt")) as fh:
         for line in fh:
             line = line.split("#", 1)[0].strip()
             if line:
@@ -85,10 +81,8 @@ def oracle_checks(R, rho):
 
 def against_oracle_steady_state(n, rho, rank):
     """Max population error against the oracle's steady state and its ranking
-    on every pair the error resolves; None where none is stored."""
+    on every pair the error resolves."""
     p_or = oracle_populations(n)
-    if p_or is None:
-        return None
     err = float(np.max(np.abs(np.diag(rho).real - p_or)))
     assert err < 1e-6, err
     assert tie_aware_same_order(p_or, rank, 2 * err + 1e-15) == 0
@@ -113,7 +107,7 @@ def tie_aware_same_order(p_ref, rank, tau):
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_config3_plain_fp64(Q, n):
+def test_ba_m4_plain_fp64(Q, n):
     g, P, R, plain, rho, lmin = workload(Q, n)
     assert plain.stats["converged"] == 1
     oracle_checks(R, rho)
@@ -122,7 +116,7 @@ def test_config3_plain_fp64(Q, n):
     # the GPU's ranking of its own state is the oracle's rank rule (exact)
     assert np.array_equal(plain.rank.cpu().numpy(), O.rank_ref(np.diag(rho).real))
     err = against_oracle_steady_state(n, rho, plain.rank.cpu().numpy())
-    assert err is None or err < 1e-7, err
+    assert err < 1e-7, err
 
 
 def _compare_with_plain(Q, n, got_rho, got_rank):
@@ -138,8 +132,8 @@ def _compare_with_plain(Q, n, got_rho, got_rank):
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_config3_batched_fp32_mixed_from_warm_start(Q, n):
-    """The spec form: qpr_batch_solve with the FP32 product and the FP64
+def test_ba_m4_batched_fp32_mixed_from_warm_start(Q, n):
+    """The batched mixed warm-start form: qpr_batch_solve with the FP32 product and the FP64
     fold-and-judge defect correction, started from the learned warm start."""
     from paper_2003_04930_amd import warmstart as W
     g, P, R, plain, rho, lmin = workload(Q, n)
@@ -153,7 +147,7 @@ def test_config3_batched_fp32_mixed_from_warm_start(Q, n):
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_config3_bf16x3(Q, n):
+def test_ba_m4_bf16x3(Q, n):
     """Three bf16 slices on the matrix cores with FP32 accumulation, FP64
     folds and judge."""
     g, P, R, plain, rho, lmin = workload(Q, n)
@@ -164,7 +158,7 @@ def test_config3_bf16x3(Q, n):
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_config3_fp32_mixed_cold(Q, n):
+def test_ba_m4_fp32_mixed_cold(Q, n):
     """The FP32 defect correction from I/N (single-system solve)."""
     g, P, R, plain, rho, lmin = workload(Q, n)
     out = Q.steady_state(P, OMEGA, DT, TOL, 400000, prec="fp32")

@@ -3,7 +3,7 @@
 tests/golden/ss_ba922_diag.txt holds the populations Re rho_aa of the
 oracle's RK4 run to ||L||_F < 1e-12 at omega = 0.2, 0.5, 0.8 (written by
 make_ss_ba922.py from oracle/ only).  Every solver form -- plain FP64 RK4,
-the paper's RKF45, and the spec form (qpr_batch_solve with the FP32
+the paper's RKF45, and the batched mixed warm-start form (qpr_batch_solve with the FP32
 defect correction from the learned warm start) -- stopped at 1e-8 must
 match it within the 1e-6 bound of the mixed solves (observed ~1e-8), have
 its residual confirmed by the oracle's right-hand side, and rank the nodes
@@ -86,7 +86,7 @@ def test_plain_fp64_matches_oracle_steady_state(Q, golden, workload, omega):
     assert err < 1e-7
 
 
-def test_north_star_form_matches_oracle(Q, golden, workload):
+def test_batched_mixed_warm_form_matches_oracle(Q, golden, workload):
     """qpr_batch_solve, FP32 steps with the FP64 fold and judge, from the
     learned warm start, the three omegas together."""
     from paper_2003_04930_amd import warmstart as W

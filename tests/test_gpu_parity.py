@@ -108,7 +108,7 @@ def test_rk4_steps_step_locked(Q, name, steps, product):
 
 # ---------------------------------------------------------- steady state
 @pytest.mark.parametrize("product", ["dense", "sparse", "fused"])
-def test_steady_state_config1_matches_oracle(Q, product):
+def test_steady_state_er16_matches_oracle(Q, product):
     g = GRAPHS["er16"]()
     P = Q.Problem.from_graph(g)
     R = oracle_problem(g)
