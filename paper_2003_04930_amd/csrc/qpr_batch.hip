@@ -1,7 +1,8 @@
 // Many independent (graph, omega) systems in one set of launches.
 //
-// Every kernel of an RK4 stage is launched once for the whole batch: a
-// persistent grid strides over a device-side list of (system, tile) items and
+// Every kernel of an RK4 stage is launched once for the whole batch over a
+// device-side list of (system, tile) items -- the products with a persistent
+// grid that strides over it, the epilogue with one workgroup per item -- and
 // each item runs the same tile code as the single-system kernels.  A chunk of
 // steps (plus, in mixed precision, the FP64 fold and judge) is captured once as
 // a HIP graph and replayed; between replays the host reads every system's
@@ -505,6 +506,11 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
 
   const bool use_gemm = !step_sparse;
   const int grid_g = 1024, grid_e = 2048, grid_f = 1024;
+  // the epilogue takes one work item per workgroup: its grid covers the whole
+  // initial list (all systems running); later, workgroups past the live count
+  // exit at once
+  build_lists();
+  const int grid_e1 = std::max(1, (int)ie.size());
   // tile configuration: tuned on this batch's own work list unless given
   int cands[8];
   const int ncand = batch_gemm_cfgs(xk, cands, 8);
@@ -563,7 +569,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
       if (e != hipSuccess) return e;
     }
     const bool finish = rkf ? (q == 0 || q == 5) : (q == 0 || q == 4);
-    return launch_epilogue_batch(xs, d_epi + (size_t)q * nsys, d_items_e, d_counts + 1, grid_e,
+    return launch_epilogue_batch(xs, d_epi + (size_t)q * nsys, d_items_e, d_counts + 1, grid_e1,
                                  d_sys_list, d_counts + 3, finish, qs);
   };
   auto enqueue_fold_judge = [&](hipStream_t qs) -> hipError_t {

@@ -716,21 +716,23 @@ __global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6
   epilogue_tile<XS, NT>(pv, a, st, partials, xcd ? xcd_contiguous(bid, nb) : bid);
 }
 
-// Persistent form for many systems (see k_gemm_k4_batch).  Each tile writes
-// its partials into its own system's buffer; k_finish_batch folds them.
+// Batched form for many systems: workgroup i takes item i of the device-side
+// (system, tile pair) list and the workgroups past its current length exit
+// at once (the grid covers the list as built, before any system stopped).
+// Without a grid-stride loop the tile code fits six waves per SIMD like the
+// single-system kernel (the loop kept 106-115 VGPRs live: four waves, and
+// 160 family systems took 9-21 % longer).  Each tile writes its partials into
+// its own system's buffer; k_finish_batch folds them.
 template <int XS>
-__global__ void __launch_bounds__(ETHREADS)
+__global__ void __launch_bounds__(ETHREADS) __attribute__((amdgpu_waves_per_eu(6, 6)))
     k_epilogue_batch(const BatchEpi* __restrict__ args, const int2* __restrict__ items,
                      const int* __restrict__ nitems) {
-  const int ni = *nitems;
-  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
-    const int2 item = items[it];
-    const BatchEpi& e = args[item.x];
-    DevState* st = e.st;
-    if (st->stop || (e.a.gate && st->hold)) continue;
-    epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y);
-    __syncthreads();
-  }
+  if ((int)blockIdx.x >= *nitems) return;
+  const int2 item = items[blockIdx.x];
+  const BatchEpi& e = args[item.x];
+  DevState* st = e.st;
+  if (st->stop || (e.a.gate && st->hold)) return;
+  epilogue_tile<XS>(e.pv, e.a, st, e.partials, item.y);
 }
 
 // Sparse commutator product X = H_off Y (FP64) through the CSR of H_off.
