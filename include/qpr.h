@@ -328,8 +328,9 @@ qpr_status qpr_steady_state(const qpr_problem* P, double omega, double dt,
  * range, NULL arrays, a repeated stream), QPR_E_WORKSPACE (a workspace too
  * small for the largest system).  Returns when every system has finished.
  * With the environment variable QPR_PROGRESS set to a number of seconds, the
- * count of finished systems is printed to stderr at most that often (and
- * when the last one finishes); unset, nothing is printed.
+ * count of finished systems is printed to stderr at most that often, and
+ * when the last one finishes if the run lasted that long; unset, nothing is
+ * printed.
  */
 qpr_status qpr_steady_state_many(int32_t count, const qpr_problem* const* probs,
                                  const double* omegas, double dt, double tol,

@@ -333,8 +333,9 @@ bool gemm_cfg_fits(int kind, int cfg, int ld);
 
 // Progress of a long batch on stderr, for callers that watch a run's output:
 // with QPR_PROGRESS=<seconds> set, report() prints "done of total" at most
-// once per that interval (and always for the last one); unset, it prints
-// nothing.  Safe to call from several worker threads.
+// once per that interval, and the final count when the run has lasted at
+// least that long; unset, it prints nothing.  Safe to call from several
+// worker threads.
 class Progress {
  public:
   explicit Progress(const char* what) : what_(what), t0_(std::chrono::steady_clock::now()) {
@@ -346,7 +347,7 @@ class Progress {
     std::lock_guard<std::mutex> lk(mu_);
     const double t =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
-    if (done < total && t - last_ < every_) return;
+    if (done < total ? t - last_ < every_ : t < every_) return;
     last_ = t;
     std::fprintf(stderr, "[qpr] %s: %d of %d systems %s after %.0f s\n", what_, done, total, unit,
                  t);

@@ -123,12 +123,16 @@ def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, mode):
 @pytest.mark.parametrize("mode,word", [("concurrent", "solved"), ("persistent", "stopped")])
 def test_batch_progress_lines(Q, capfd, monkeypatch, mode, word):
     """QPR_PROGRESS=<seconds> makes a batch print how many systems are done
-    (always the last count); unset, it prints nothing."""
+    (the final count once the run has lasted the interval); unset, or with
+    an interval longer than the run, it prints nothing."""
     items = [(Q.Problem.from_graph(g), 0.5) for g in small_family()[:3]]
     monkeypatch.delenv("QPR_PROGRESS", raising=False)
     Q.batch_solve(items, tol=1e-8, mode=mode)
     assert "[qpr]" not in capfd.readouterr().err
     monkeypatch.setenv("QPR_PROGRESS", "1000")
+    Q.batch_solve(items, tol=1e-8, mode=mode)
+    assert "[qpr]" not in capfd.readouterr().err
+    monkeypatch.setenv("QPR_PROGRESS", "1e-6")
     Q.batch_solve(items, tol=1e-8, mode=mode)
     err = capfd.readouterr().err
     assert f"[qpr] {mode} batch: 3 of 3 systems {word} after" in err
