@@ -159,7 +159,8 @@ typedef struct {
                           single precision, arithmetic FP64; needs the sparse
                           product), 0 = FP32 with QPR_PRODUCT_AUTO where the
                           product is sparse, else FP64 [0].  qpr_steady_state,
-                          qpr_steady_state_many and the concurrent batch form  */
+                          qpr_steady_state_many and both batch forms (the
+                          persistent one decides on the largest system)     */
   int32_t reserved;
 } qpr_opts;
 
@@ -370,8 +371,9 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *    stages, FP64 and FP32, run as fused epilogues); the dense-product tile
  *    configuration is tuned on this batch's own work list unless
  *    opts->gemm_cfg >= 0.  FP64: bitwise the lone solves; FP32: the defect
- *    is held in FP64 whatever opts->delta_state says (the lone FP32 solve's
- *    default holds it in FP32, so step counts can differ slightly).
+ *    held as opts->delta_state says, as in the lone solve (its fold of the
+ *    defect into the anchor is one kernel here, so the step counts can
+ *    differ slightly from the lone solve's).
  *   probs, omegas, rhos, ranks  HOST arrays of nsys entries; rhos[k] are
  *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
  *           may be NULL or hold device int32[n_k] / NULL entries

@@ -35,6 +35,7 @@ struct BatchFold {      // one system's fold: rho_a = (rho_a + delta) / tr, delt
   float *lo_r, *lo_i;
   int n, ld, renorm;
   DevState* st;
+  float *d32_r, *d32_i;  // the defect held in FP32 (then dn_r / dn_i are unused), or null
 };
 
 // st->aux[0] = tr(rho_a + delta) from the two diagonals; one item per system
@@ -68,12 +69,20 @@ __global__ void __launch_bounds__(256) k_fold_batch(const BatchFold* __restrict_
     for (int e = threadIdx.x; e < TE * F.ld; e += 256) {
       const int a = r0 + e / F.ld, b = e % F.ld;
       const size_t o = (size_t)a * F.ld + b;
-      const double vr = (F.an_r[o] + F.dn_r[o]) * inv;
-      const double vi = (F.an_i[o] + F.dn_i[o]) * inv;
+      double vr, vi;
+      if (F.d32_r) {
+        vr = (F.an_r[o] + (double)F.d32_r[o]) * inv;
+        vi = (F.an_i[o] + (double)F.d32_i[o]) * inv;
+        F.d32_r[o] = 0.f;
+        F.d32_i[o] = 0.f;
+      } else {
+        vr = (F.an_r[o] + F.dn_r[o]) * inv;
+        vi = (F.an_i[o] + F.dn_i[o]) * inv;
+        F.dn_r[o] = 0.0;
+        F.dn_i[o] = 0.0;
+      }
       F.an_r[o] = vr;
       F.an_i[o] = vi;
-      F.dn_r[o] = 0.0;
-      F.dn_i[o] = 0.0;
       if (F.lo_r) {
         F.lo_r[o] = 0.f;
         F.lo_i[o] = 0.f;
@@ -313,8 +322,18 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   // the FP32 steps fused too (gathers of the FP32 state copy inside the tile
   // kernel): 5.85 against 4.07 solves/s over the same 160 systems
   const bool fuse32 = fuse;
-  const int xs_step = mixed ? (step_sparse && fuse32 ? XS_FUSED32 : XS_DENSE32)
-                            : step_sparse ? (fuse ? XS_FUSED64 : XS_SPARSE64) : XS_DENSE64;
+  // the defect held in FP32 (every state plane of the FP32 steps single
+  // precision), as the lone mixed solve does by default with the sparse
+  // product: half the bytes per stage
+  if (mixed && (o.delta_state < 0 || o.delta_state > 2))
+    return fail(QPR_E_ARG, "delta_state must be 0, 1 or 2 (got %d)", o.delta_state);
+  if (mixed && o.delta_state == 2 && !step_sparse)
+    return fail(QPR_E_ARG, "an FP32 defect needs the sparse product");
+  const bool state32 = mixed && step_sparse &&
+                       (o.delta_state == 2 || (o.delta_state == 0 && o.product == QPR_PRODUCT_AUTO));
+  const int xs_step = state32 ? XS_FUSED32S
+                      : mixed ? (step_sparse && fuse32 ? XS_FUSED32 : XS_DENSE32)
+                      : step_sparse ? (fuse ? XS_FUSED64 : XS_SPARSE64) : XS_DENSE64;
   const int xs_judge = judge_sparse ? (fuse ? XS_FUSED64 : XS_SPARSE64) : XS_DENSE64;
 
   // host argument tables: slots 0..3 = RK4 stages, 4 = judge / RHS; or the six
@@ -413,6 +432,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
         }
         a.check = q == 0 ? (mixed ? CHK_DELTA : CHK_PLAIN) : CHK_NONE;
         a.gate = mixed ? 1 : 0;
+        if (state32) a = rk4_stage_args_f32s(w, q, omegas[k], dt, CHK_DELTA, 1);
       } else {  // judge: r_a = L(rho_a) with the FP64 product
         g.H = P->h_off;
         g.yr = w.an_r;
@@ -430,11 +450,16 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
         a.mode = EPI_RHS;
         a.xkind = xs_judge;
         a.check = CHK_JUDGE;
+        if (state32) {  // and the FP32 copy of r_a the FP32 steps add
+          a.lor = w.ra32_r;
+          a.loi = w.ra32_i;
+        }
       }
     }
     hf[k] = BatchFold{w.an_r, w.an_i, w.yn_r, w.yn_i, w.p_a, w.p_n,
-                      mixed ? w.lo_r : nullptr, mixed ? w.lo_i : nullptr,
-                      P->n, P->ld, o.renorm ? 1 : 0, w.st};
+                      mixed && !state32 ? w.lo_r : nullptr, mixed && !state32 ? w.lo_i : nullptr,
+                      P->n, P->ld, o.renorm ? 1 : 0, w.st,
+                      state32 ? w.dn_r : nullptr, state32 ? w.dn_i : nullptr};
   }
   QPR_HIP(hipMemcpyAsync(d_gemm, hg.data(), hg.size() * sizeof(BatchGemm), hipMemcpyHostToDevice, s));
   QPR_HIP(hipMemcpyAsync(d_epi, he.data(), he.size() * sizeof(BatchEpi), hipMemcpyHostToDevice, s));
@@ -554,8 +579,10 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
     const bool judge = !rkf && q == 4;
     const bool gemm = judge ? !judge_sparse : use_gemm;
     const int xs = judge ? xs_judge : xs_step;
+    // the fused kinds gather inside the epilogue: no product launch (the FP32
+    // product would read the FP32 copy, which the FP32-state stages do not keep)
     const bool spmm = (judge ? judge_sparse : step_sparse) && xs != XS_FUSED64 &&
-                      xs != XS_FUSED32;
+                      xs != XS_FUSED32 && xs != XS_FUSED32S;
     if (spmm) {
       e = mixed && !judge
               ? launch_spmm_f32_batch(d_epi + (size_t)q * nsys, d_items_s, d_counts + 4, grid_e, qs)

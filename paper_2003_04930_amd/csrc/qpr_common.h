@@ -288,6 +288,9 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
 // largest step whose fourth-order update is stable for the spectrum bound of
 // the Liouvillian at omega (rho_h = spectral radius of H).
 EpiArgs rkf_stage_args(const Ws& w, int st, double omega, int xs);
+// classical RK4 stage k of the mixed solve's defect step with the defect held
+// in FP32 (XS_FUSED32S, every state plane single precision)
+EpiArgs rk4_stage_args_f32s(const Ws& w, int k, double omega, double dt, int check, int gate);
 
 // Concurrent single-system solves: `nworkers` host threads, worker w on
 // streams[w] with workspace ws[w] (each large enough for the largest system),

@@ -390,8 +390,7 @@ static hipError_t enqueue_rhs(const qpr_problem* P, const Ws& w, const ProbView&
 // the ping-pong stage states, the accumulator, the FP32 copy of r_a); the
 // stage gathers X from its FP32 input; arithmetic in FP64.  Same rotation as
 // rk4_stage_args: delta_n -> D_1 -> D_2 -> D_1 -> delta_n.
-static EpiArgs rk4_stage_args_f32s(const Ws& w, int k, double omega, double dt, int check,
-                                   int gate) {
+EpiArgs rk4_stage_args_f32s(const Ws& w, int k, double omega, double dt, int check, int gate) {
   float* in_r[4] = {w.dn_r, w.d1_r, w.d2_r, w.d1_r};
   float* in_i[4] = {w.dn_i, w.d1_i, w.d2_i, w.d1_i};
   float* out_r[4] = {w.d1_r, w.d2_r, w.d1_r, w.dn_r};

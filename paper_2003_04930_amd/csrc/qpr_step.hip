@@ -1471,6 +1471,8 @@ hipError_t launch_epilogue_batch(int xsource, const BatchEpi* args, const int2* 
     k_epilogue_batch<XS_FUSED64><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else if (xsource == XS_FUSED32)
     k_epilogue_batch<XS_FUSED32><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
+  else if (xsource == XS_FUSED32S)  // the defect held in FP32
+    k_epilogue_batch<XS_FUSED32S><<<grid, ETHREADS, 0, s>>>(args, items, nitems);
   else
     return hipErrorInvalidValue;
   if (finish) k_finish_batch<<<256, FOLD_THREADS, 0, s>>>(args, sys_list, nsys);

@@ -100,15 +100,23 @@ def test_batch_graph_replay_equals_eager(Q):
 
 
 @pytest.mark.parametrize("mode", ["persistent", "auto"])
-@pytest.mark.parametrize("product", ["sparse", "dense", "fused"])
-def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, mode):
+@pytest.mark.parametrize("product,delta", [("sparse", "auto"), ("dense", "auto"),
+                                           ("fused", "auto"), ("auto", "fp32"),
+                                           ("auto", "fp64")])
+def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, delta, mode):
+    """Every product form, and the defect held in FP32 (the default with the
+    sparse product) or FP64, in both batch forms."""
     gs = small_family()
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.1, 0.9)]
-    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32, product=product, mode=mode)
+    if delta == "fp32":
+        items = items[6:]   # the three smallest graphs are dense (> 5 %): no FP32 defect
+    out = Q.batch_solve(items, prec="fp32", tol=1e-8, chunk=32, product=product, mode=mode,
+                        delta_state=delta)
     # the persistent form tunes the dense FP32 product on the batch (the
     # sparse one has no tiles); the concurrent form uses the solver's defaults
     assert (out.tuned_cfg >= 0) == (product == "dense" and mode == "persistent")
-    for k, ((P, w), g) in enumerate(zip(items, [g for g in gs for _ in (0.1, 0.9)])):
+    graphs = [g for g in gs for _ in (0.1, 0.9)][len([g for g in gs for _ in (0.1, 0.9)]) - len(items):]
+    for k, ((P, w), g) in enumerate(zip(items, graphs)):
         st = out.stats[k]
         assert st["converged"] == 1 and st["folds"] >= 1
         rho = Q.to_complex(out.rhos[k])
