@@ -195,8 +195,10 @@ typedef enum {
 
 /* How qpr_batch_solve runs its systems. */
 typedef enum {
-  QPR_BATCH_AUTO = 0,       /* the concurrent form: faster than the persistent one on
-                               every batch measured (3 to 1,280 systems)               */
+  QPR_BATCH_AUTO = 0,       /* the persistent form for QPR_FP32 batches of 8 or more
+                               systems with QPR_PRODUCT_AUTO and the defect not forced
+                               to FP64 (1.2-1.35x faster there), else the concurrent
+                               form (faster on every FP64 batch measured)              */
   QPR_BATCH_PERSISTENT = 1, /* shared persistent launches over (system, tile) work lists,
                                chunks replayed as one captured graph for all systems   */
   QPR_BATCH_CONCURRENT = 2  /* single-system solves on a pool of worker streams, as

@@ -171,9 +171,22 @@ BatchLayout batch_layout(int nsys, const int* ns, int prec, int gtile, bool rkf)
   return L;
 }
 
-// The concurrent form (QPR_BATCH_AUTO, QPR_BATCH_CONCURRENT): its workers and
-// the arena of one single-system workspace per worker.
-bool batch_concurrent(const qpr_opts* o) { return !o || o->batch_mode != QPR_BATCH_PERSISTENT; }
+// Which form runs.  QPR_BATCH_AUTO takes the persistent form for FP32
+// batches of eight or more systems whose defect may be held in FP32 (product
+// QPR_PRODUCT_AUTO, delta_state not FP64): with the FP32 defect it runs
+// 1.2-1.35x the concurrent form's solves/s from 10 to 1,280 family systems.
+// Otherwise the concurrent form, faster on every FP64 batch and on three
+// N = 922 systems.  Decided from what the workspace query also sees.
+bool batch_concurrent(const qpr_opts* o, int prec, int nsys) {
+  const int mode = o ? o->batch_mode : QPR_BATCH_AUTO;
+  if (mode != QPR_BATCH_AUTO) return mode != QPR_BATCH_PERSISTENT;
+  const bool fp32_state = prec == QPR_FP32 && nsys >= 8 &&
+                          (!o || (o->product == QPR_PRODUCT_AUTO && o->delta_state != 1 &&
+                                  o->integrator != QPR_RKF45));
+  return !fp32_state;
+}
+// The concurrent form: its workers and the arena of one single-system
+// workspace per worker.
 int batch_workers(int nsys, const qpr_opts* o) {
   const int w = o && o->batch_workers > 0 ? o->batch_workers : 8;
   return std::max(1, std::min(std::min(w, nsys), kMaxWorkers));
@@ -196,7 +209,7 @@ extern "C" size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int3
     if (n[s] < 2) return 0;
   const bool rkf = opts && opts->integrator == QPR_RKF45;
   if (rkf && prec != QPR_FP64) return 0;
-  if (batch_concurrent(opts))
+  if (batch_concurrent(opts, prec, nsys))
     return batch_workers(nsys, opts) * worker_ws_stride(nsys, n, prec, rkf);
   return batch_layout(nsys, n, prec, 32, rkf).total;
 }
@@ -231,7 +244,7 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   if (opts) o = *opts;
   if (o.batch_mode < QPR_BATCH_AUTO || o.batch_mode > QPR_BATCH_CONCURRENT)
     return fail(QPR_E_ARG, "unknown batch_mode %d", o.batch_mode);
-  const bool concurrent = batch_concurrent(&o);
+  const bool concurrent = batch_concurrent(&o, prec, nsys);
   if (!concurrent && o.product == QPR_PRODUCT_BLOCKSPARSE)
     return fail(QPR_E_ARG, "the persistent batch form has no block-sparse product");
   if (o.chunk <= 0) o.chunk = concurrent ? 64 : 32;

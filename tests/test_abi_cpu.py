@@ -165,6 +165,18 @@ def test_batch_workspace_query_and_mode_check():
     pers = L.qpr_batch_workspace_bytes(3, ns, 0, C.byref(qpr.make_opts(batch_mode="persistent")))
     assert pers > 0 and pers != 3 * one
     assert L.qpr_batch_workspace_bytes(3, ns, 2, None) == 0      # no BF16x3 batch
+    # AUTO: FP32 batches of eight or more systems take the persistent form
+    # (unless the defect is forced to FP64 or a product is named)
+    n8 = (C.c_int32 * 8)(*([40, 922, 75] * 3)[:8])
+    n7 = (C.c_int32 * 7)(*([40, 922, 75] * 3)[:7])
+    one32 = L.qpr_workspace_bytes(922, 1, 0)
+    persist8 = L.qpr_batch_workspace_bytes(8, n8, 1, C.byref(qpr.make_opts(batch_mode="persistent")))
+    assert L.qpr_batch_workspace_bytes(8, n8, 1, C.byref(qpr.make_opts())) == persist8
+    assert L.qpr_batch_workspace_bytes(8, n8, 1, None) == persist8
+    assert L.qpr_batch_workspace_bytes(7, n7, 1, C.byref(qpr.make_opts())) == 7 * one32
+    assert L.qpr_batch_workspace_bytes(8, n8, 0, C.byref(qpr.make_opts())) == 8 * one
+    for kw in (dict(delta_state="fp64"), dict(product="fused")):
+        assert L.qpr_batch_workspace_bytes(8, n8, 1, C.byref(qpr.make_opts(**kw))) == 8 * one32
     P = qpr.qpr_problem()
     P.n, P.ld, P.h_off = 100, 128, C.c_void_p(256)
     op = qpr.make_opts()

@@ -99,7 +99,7 @@ def test_batch_graph_replay_equals_eager(Q):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("mode", ["persistent", "auto"])
+@pytest.mark.parametrize("mode", ["persistent", "concurrent"])
 @pytest.mark.parametrize("product,delta", [("sparse", "auto"), ("dense", "auto"),
                                            ("fused", "auto"), ("auto", "fp32"),
                                            ("auto", "fp64")])
@@ -126,6 +126,20 @@ def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, delta, mode):
         assert abs(np.trace(rho).real - 1) < 1e-12
         if g.n <= 130:
             assert np.max(np.abs(rho - _oracle_steady(g, w))) < 1e-6
+
+
+def test_auto_batch_form(Q, capfd, monkeypatch):
+    """AUTO runs FP32 batches of eight or more systems in the persistent form
+    (the defect in FP32) and smaller or FP64 batches concurrently; the form
+    shows in the progress line."""
+    gs = small_family()[3:]
+    items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.3, 0.5, 0.7)]  # 9 systems
+    monkeypatch.setenv("QPR_PROGRESS", "1e-6")
+    for prec, its, form in (("fp32", items, "persistent"), ("fp32", items[:7], "concurrent"),
+                            ("fp64", items, "concurrent")):
+        out = Q.batch_solve(its, prec=prec, tol=1e-8)
+        assert all(s["converged"] == 1 for s in out.stats)
+        assert f"[qpr] {form} batch: {len(its)} of {len(its)}" in capfd.readouterr().err, (prec, len(its))
 
 
 @pytest.mark.parametrize("mode,word", [("concurrent", "solved"), ("persistent", "stopped")])
