@@ -101,11 +101,13 @@ def test_batch_graph_replay_equals_eager(Q):
 
 @pytest.mark.parametrize("mode", ["persistent", "concurrent"])
 @pytest.mark.parametrize("product,delta", [("sparse", "auto"), ("dense", "auto"),
-                                           ("fused", "auto"), ("auto", "fp32"),
-                                           ("auto", "fp64")])
+                                           ("fused", "auto"), ("auto", "auto"),
+                                           ("auto", "fp32"), ("auto", "fp64")])
 def test_fp32_batch_meets_fp64_judge_and_oracle(Q, product, delta, mode):
     """Every product form, and the defect held in FP32 (the default with the
-    sparse product) or FP64, in both batch forms."""
+    sparse product) or FP64, in both batch forms.  With both left to AUTO the
+    persistent form holds the defect in FP32 for every system (decided on the
+    largest, sparse one), the dense small graphs included."""
     gs = small_family()
     items = [(Q.Problem.from_graph(g), w) for g in gs for w in (0.1, 0.9)]
     if delta == "fp32":
