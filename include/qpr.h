@@ -358,8 +358,11 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  * qpr_steady_state with a step size and step control per system (dt = first
  * step, cap from the system's spectral bound unless opts->dt_max > 0).
  * prec QPR_FP64 or QPR_FP32 (the FP32 product with the FP64 fold-and-judge
- * defect correction of qpr_steady_state).  Two forms (opts->batch_mode):
- *  - concurrent (QPR_BATCH_AUTO, QPR_BATCH_CONCURRENT): single-system solves
+ * defect correction of qpr_steady_state).  Two forms (opts->batch_mode;
+ * QPR_BATCH_AUTO takes the persistent one for QPR_FP32 batches of 8 or more
+ * systems with QPR_PRODUCT_AUTO and delta_state not 1, the concurrent one
+ * otherwise):
+ *  - concurrent (QPR_BATCH_CONCURRENT): single-system solves
  *    on a pool of opts->batch_workers worker threads, each with a stream of
  *    its own (created here, ordered after `stream`) and a workspace of its
  *    own carved from ws, as qpr_steady_state_many; each system bitwise its
