@@ -23,15 +23,19 @@
  *  - Status codes: QPR_OK (0) or a negative qpr_status; no C++ exception
  *    crosses the ABI; qpr_last_error() returns this thread's message for the
  *    last non-OK status.
- *  - Memory: the library never allocates or frees device memory.  The caller
- *    owns a problem arena (qpr_problem_bytes) and a workspace
- *    (qpr_workspace_bytes); both are device memory, 256-byte aligned.
+ *  - Memory: the library never allocates or frees device memory at run time.
+ *    The caller owns a problem arena (qpr_problem_bytes) and a workspace
+ *    (qpr_workspace_bytes); both are device memory, 256-byte aligned.  The one
+ *    exception is the static per-GPU array of qpr_rk4_step_noalloc, which the
+ *    code object brings with it.  Solves read their control blocks back
+ *    through small pinned host buffers (hipHostMalloc, freed before return).
  *  - Density matrices cross the ABI as planar FP64 device arrays of 2*n*n
  *    doubles: rho[a*n+b] = Re rho_ab, rho[n*n + a*n+b] = Im rho_ab (row-major,
  *    rho_ab = <a|rho|b>).  They must be Hermitian.
  *  - Streams: every call enqueues on `stream` (NULL = the null stream).
  *    qpr_rhs and qpr_rk4_step are asynchronous; qpr_build_google,
- *    qpr_steady_state and qpr_batch_solve synchronise the stream.
+ *    qpr_steady_state, qpr_steady_state_many and qpr_batch_solve synchronise
+ *    the streams they use.
  *  - Concurrency: calls that share a workspace must not overlap.
  */
 #ifndef QPR_H
