@@ -183,7 +183,7 @@ typedef enum {
                              choice is FUSED for the FP32 steps of the mixed solve, and for
                              FP64 stages from a padded size of 4096 on, in qpr_batch_solve,
                              and in qpr_steady_state_many while two or more systems run */
-  QPR_PRODUCT_DENSE = 1,  /* dense MFMA product + fused epilogue (two launches per stage) */
+  QPR_PRODUCT_DENSE = 1,  /* dense MFMA product, then the epilogue (two launches per stage) */
   QPR_PRODUCT_SPARSE = 2, /* CSR gathers: X row a = sum of the rows of rho listed for a in H_off */
   QPR_PRODUCT_FUSED = 3,  /* the same gathers inside the epilogue: each tile pair gathers the two
                              32 x 32 blocks of X it needs into LDS, so X never goes to HBM and a
