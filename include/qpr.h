@@ -145,7 +145,8 @@ typedef struct {
   int32_t use_graph;  /* replay each chunk as a captured HIP graph [1]        */
   int32_t fold_every; /* mixed precision: steps between FP64 folds [=chunk]   */
   int32_t renorm;     /* mixed precision: divide by the trace at folds [1]    */
-  int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1]  */
+  int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1];
+                         qpr_batch_solve's persistent form has its own three   */
   int32_t product;    /* qpr_product [QPR_PRODUCT_AUTO]                       */
   int32_t integrator; /* qpr_integrator [QPR_RK4]                             */
   int32_t sparse_variant; /* sparse product kernel variant + 1, 0 = default [0];
@@ -377,9 +378,11 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *    replayed as one captured HIP graph, and between replays the lists are
  *    shrunk to the systems still running; the product follows opts->product,
  *    decided on the largest system's density for the whole batch (with AUTO the sparse
- *    stages, FP64 and FP32, run as fused epilogues); the dense-product tile
- *    configuration is tuned on this batch's own work list unless
- *    opts->gemm_cfg >= 0.  FP64: bitwise the lone solves; FP32: the defect
+ *    stages, FP64 and FP32, run as fused epilogues); a dense product runs one
+ *    of three tile configurations per precision (64 x 64 tiles with 16- or
+ *    32-deep k-slabs, 32 x 32 tiles): opts->gemm_cfg 0..2 picks it (larger is
+ *    QPR_E_ARG), a negative value times each on this batch's own work list
+ *    and takes the fastest.  FP64: bitwise the lone solves; FP32: the defect
  *    held as opts->delta_state says, as in the lone solve (its fold of the
  *    defect into the anchor is one kernel here, so the step counts can
  *    differ slightly from the lone solve's).
@@ -387,8 +390,9 @@ size_t qpr_batch_workspace_bytes(int32_t nsys, const int32_t* n, int32_t prec,
  *           device planar 2*n_k*n_k FP64 (in: rho0, out: steady state); ranks
  *           may be NULL or hold device int32[n_k] / NULL entries
  *   stats   HOST qpr_stats[nsys] or NULL (per-system status in stats[k].status)
- *   tuned_cfg  HOST int32 or NULL: the tuned product configuration of the
- *           persistent form (-1: none, and always -1 in the concurrent form)
+ *   tuned_cfg  HOST int32 or NULL: the persistent form's dense tile
+ *           configuration, as the index opts->gemm_cfg takes (-1 without a
+ *           dense product, and always -1 in the concurrent form)
  *   tune_cache  HOST path or NULL: a cache written by qpr_autotune, loaded
  *           (qpr_load_tuning) before the solve, so its dense tiles, sparse
  *           variants and stage forms are the ones the batch uses; NULL keeps

@@ -348,6 +348,12 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
                       : mixed ? (step_sparse && fuse32 ? XS_FUSED32 : XS_DENSE32)
                       : step_sparse ? (fuse ? XS_FUSED64 : XS_SPARSE64) : XS_DENSE64;
   const int xs_judge = judge_sparse ? (fuse ? XS_FUSED64 : XS_SPARSE64) : XS_DENSE64;
+  // the dense product's tile configurations at this precision
+  int cands[8];
+  const int ncand = batch_gemm_cfgs(xk, cands, 8);
+  if (!step_sparse && o.gemm_cfg >= ncand)
+    return fail(QPR_E_ARG, "gemm_cfg %d: the batched product has %d tile configurations at "
+                "this precision", o.gemm_cfg, ncand);
 
   // host argument tables: slots 0..3 = RK4 stages, 4 = judge / RHS; or the six
   // Fehlberg stages
@@ -501,7 +507,9 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ns[a] > ns[b]; });
   int gtile = 64;
-  int gcfg = -1;
+  int gcfg = -1;  // index into the batch kernel table
+  int gpick = -1; // the same as an index into this precision's candidates (what
+                  // opts->gemm_cfg takes and tuned_cfg reports)
   std::vector<int2> ig, ie, iff, isp;
   std::vector<int> sl;
   std::vector<char> active(nsys, 1);
@@ -550,11 +558,10 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
   build_lists();
   const int grid_e1 = std::max(1, (int)ie.size());
   // tile configuration: tuned on this batch's own work list unless given
-  int cands[8];
-  const int ncand = batch_gemm_cfgs(xk, cands, 8);
   if (use_gemm) {
-    if (o.gemm_cfg >= 0 && o.gemm_cfg < ncand) {
-      gcfg = cands[o.gemm_cfg];
+    if (o.gemm_cfg >= 0) {
+      gpick = o.gemm_cfg;
+      gcfg = cands[gpick];
     } else {
       HipEvent ev0, ev1;
       QPR_HIP(hipEventCreate(&ev0.h));
@@ -578,12 +585,13 @@ extern "C" qpr_status qpr_batch_solve(int32_t nsys, const qpr_problem* const* pr
         if (ms < best) {
           best = ms;
           gcfg = cands[c];
+          gpick = c;
         }
       }
     }
     gtile = batch_gemm_tile(gcfg);
   }
-  if (tuned_cfg) *tuned_cfg = gcfg;
+  if (tuned_cfg) *tuned_cfg = gpick;
   build_lists();
   QPR_HIP(upload_lists());
 

@@ -83,6 +83,25 @@ def test_rkf45_batch_equals_single_solves(Q, product, mode):
         assert torch.equal(out.ranks[k], ref.rank)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_persistent_dense_tile_choice_round_trips(Q, prec):
+    """The persistent form reports its dense tile configuration as the index
+    gemm_cfg takes: given back, that configuration is used as is (the same
+    index reported, bitwise the same states); an index past its three is
+    refused."""
+    items = [(Q.Problem.from_graph(g), 0.5) for g in small_family()[:4]]
+    a = Q.batch_solve(items, prec=prec, tol=1e-8, chunk=16, product="dense", mode="persistent")
+    assert 0 <= a.tuned_cfg <= 2
+    b = Q.batch_solve(items, prec=prec, tol=1e-8, chunk=16, product="dense", mode="persistent",
+                      gemm_cfg=a.tuned_cfg)
+    assert b.tuned_cfg == a.tuned_cfg
+    for x, y in zip(a.rhos, b.rhos):
+        assert torch.equal(x, y)
+    with pytest.raises(Q.QprError) as e:
+        Q.batch_solve(items, prec=prec, tol=1e-8, product="dense", mode="persistent", gemm_cfg=3)
+    assert e.value.status == Q.QPR_E_ARG
+
+
 def test_rkf45_batch_rejects_low_precision(Q):
     P = Q.Problem.from_graph(inputs.er_digraph(20, 0.2, seed=0))
     with pytest.raises(Q.QprError) as e:
