@@ -145,7 +145,10 @@ typedef struct {
   int32_t use_graph;  /* replay each chunk as a captured HIP graph [1]        */
   int32_t fold_every; /* mixed precision: steps between FP64 folds [=chunk]   */
   int32_t renorm;     /* mixed precision: divide by the trace at folds [1]    */
-  int32_t gemm_cfg;   /* product tile configuration, -1 = tuned default [-1];
+  int32_t gemm_cfg;   /* product tile configuration (qpr_product_configs), -1 =
+                         tuned default [-1]; an index past the table takes the
+                         default, a tile that does not divide the padded size
+                         configuration 0 (64 x 64, divides every padded size);
                          qpr_batch_solve's persistent form has its own three   */
   int32_t product;    /* qpr_product [QPR_PRODUCT_AUTO]                       */
   int32_t integrator; /* qpr_integrator [QPR_RK4]                             */
